@@ -1,0 +1,215 @@
+"""Throughput of C := C + A.B mod p on Morton-hybrid operands (one MI355X).
+
+One step = one whole product through the C ABI (planner, limb packing,
+int8 MFMA GEMM and the mod-p epilogue) with the operands already resident in
+HBM in Morton-hybrid layout.  Prints one JSON line:
+  value  = modular GOPS (2mnk / s) of the timed steps, whole job;
+  roofline = the dominant kernel (the limb GEMM) against the int8 MFMA peak,
+             its average duration taken from HIP events the library records
+             on the stream it launches on;
+  plain  = the plain uint32 kernel on the same workload (the comparator);
+  cpu_baseline = the CPU oracle (triple loop, 128-bit accumulators) on a
+             bounded sample of output rows of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "modular GOPS (2mnk/s) for C+=A·B mod p, MFMA/batched vs plain, bit-exact"
+INT8_PEAK_TOPS = 5000.0   # MI355X dense int8 MFMA, 5.0 POP/s
+P31 = 2**31 - 1
+
+WORKLOADS = {
+    # 8192^3 aligned product at the large prime: four 8-bit limbs, one k-block
+    "modp_8192cube_p2^31-1_T64": dict(N=8192, T=64, p=P31, m=8192, k=8192, n=8192,
+                                      off=(0, 0, 0, 0, 0, 0), seeds=(4001, 4002, 4003)),
+    # 4096^3 aligned product at p = 65521: two limbs
+    "modp_4096cube_p65521_T64": dict(N=4096, T=64, p=65521, m=4096, k=4096, n=4096,
+                                     off=(0, 0, 0, 0, 0, 0), seeds=(2001, 2002, 2003)),
+    # non-aligned rectangular blocks of 8192^2 parents
+    "modp_nonaligned_8192parents_p65521_T64": dict(
+        N=8192, T=64, p=65521, m=6000, k=3000, n=5000,
+        off=(64, 33, 1000, 1500, 517, 2048), seeds=(3001, 3002, 3003)),
+}
+DEFAULT = "modp_8192cube_p2^31-1_T64"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_threads() -> int:
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline(A_dev, B_dev, W, budget_s=12.0):
+    """Oracle on a bounded sample of output rows; returns the cpu_baseline object."""
+    import numpy as np
+    import torch
+
+    import oracle
+
+    p, m, k, n = W["p"], W["m"], W["k"], W["n"]
+    rc, cc, ra, ca, rb, cb = W["off"]
+    nt = cpu_threads()
+    Bh = B_dev[rb:rb + k, cb:cb + n].contiguous().cpu().numpy().view(np.uint32)
+    Bh = np.ascontiguousarray(Bh)
+
+    def run(rows):
+        Ah = np.ascontiguousarray(
+            A_dev[ra:ra + rows, ca:ca + k].contiguous().cpu().numpy().view(np.uint32))
+        Ch = np.zeros((rows, n), np.uint32)
+        t0 = time.perf_counter()
+        oracle.matmul_modp(Ch, Ah, Bh, p, nthreads=nt)
+        return time.perf_counter() - t0
+
+    probe = max(1, min(m, nt))
+    t = run(probe)
+    rows = int(min(m, max(probe, budget_s / max(t, 1e-6) * probe)))
+    rows = max(probe, (rows // nt) * nt) if rows >= nt else rows
+    t = run(rows) if rows != probe else t
+    gops = 2.0 * rows * n * k / t / 1e9
+    return {"value": gops, "unit": "GOPS", "cores": nt, "kind": "oracle",
+            "sample": "%d of %d output rows (all %d columns, k=%d), %.1f s" % (rows, m, n, k, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X and has no "
+              "multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1705_04807_amd as mh
+    from seeded_inputs import residues_torch
+
+    W = WORKLOADS[args.workload]
+    N, T, p, m, k, n = W["N"], W["T"], W["p"], W["m"], W["k"], W["n"]
+    rc, cc, ra, ca, rb, cb = W["off"]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    sh = stream.cuda_stream
+    ctx = mh.mh_ctx_create(0)
+
+    log("generating %s" % args.workload)
+    cart = {}
+    parents = {}
+    for name, seed in zip("ABC", W["seeds"]):
+        X = residues_torch(seed, p, N, N, device="cuda")
+        cart[name] = X
+        Y = torch.empty(N * N, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        mh.check(mh.mh_layout_from_cartesian(ctx, Y.data_ptr(), X.data_ptr(), N, N, T, sh))
+        parents[name] = Y
+    torch.cuda.synchronize()
+    stream.synchronize()
+
+    def step(mode):
+        mh.check(mh.mh_matmul_modp(ctx, parents["C"].data_ptr(), N, rc, cc,
+                                   parents["A"].data_ptr(), N, ra, ca, parents["B"].data_ptr(), N,
+                                   rb, cb, m, k, n, p, T, mode, sh), "mh_matmul_modp")
+
+    work = 2.0 * m * n * k
+    s, info = mh.mh_plan_describe(N, rc, cc, N, ra, ca, N, rb, cb, m, k, n, p, T,
+                                  mh.MH_MODE_LIMB_I8)
+    mh.check(s)
+    L = info.limbs
+
+    # ---- limb MFMA form (the headline)
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        step(mh.MH_MODE_LIMB_I8)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    mh.mh_ctx_set_timing(ctx, True)
+    for kk in range(mh.MH_K_COUNT):
+        mh.mh_ctx_kernel_time(ctx, kk, reset=True)
+    log("timing %d steps" % args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(mh.MH_MODE_LIMB_I8)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    gemm_ms, gemm_n = mh.mh_ctx_kernel_time(ctx, mh.MH_K_GEMM_LIMB, reset=True)
+    pack_ms, pack_n = mh.mh_ctx_kernel_time(ctx, mh.MH_K_PACK, reset=True)
+    mh.mh_ctx_set_timing(ctx, False)
+    ms_per_step = elapsed / args.steps * 1e3
+    value = work * args.steps / elapsed / 1e9
+    gemm_avg = gemm_ms / max(gemm_n, 1)
+    int8_tops = L * L * work / (gemm_avg * 1e-3) / 1e12
+    log("limb: %.3f ms/step, gemm %.3f ms, pack %.3f ms" % (ms_per_step, gemm_avg,
+                                                           pack_ms / max(pack_n, 1)))
+
+    # ---- plain uint32 kernel (comparator)
+    plain = None
+    if args.plain_steps > 0:
+        step(mh.MH_MODE_PLAIN_U32)
+        stream.synchronize()
+        mh.mh_ctx_set_timing(ctx, True)
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            step(mh.MH_MODE_PLAIN_U32)
+        stream.synchronize()
+        pe = time.perf_counter() - t0
+        pg_ms, pg_n = mh.mh_ctx_kernel_time(ctx, mh.MH_K_GEMM_PLAIN, reset=True)
+        mh.mh_ctx_kernel_time(ctx, mh.MH_K_PACK, reset=True)
+        mh.mh_ctx_set_timing(ctx, False)
+        plain = {"value": work * args.plain_steps / pe / 1e9, "unit": "GOPS",
+                 "ms_per_step": pe / args.plain_steps * 1e3,
+                 "gemm_ms": pg_ms / max(pg_n, 1)}
+        plain["limb_speedup"] = value / plain["value"]
+        log("plain: %.3f ms/step" % plain["ms_per_step"])
+    assert mh.mh_ctx_last_device_error(ctx) == 0
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        cpu = cpu_baseline(cart["A"], cart["B"], W)
+    mh.mh_ctx_destroy(ctx)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "GOPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "k": k, "n": n, "p": p, "T": T,
+                   "parents": N, "offsets_c_a_b": list(W["off"]), "limbs": L,
+                   "mode": "limb_i8", "tile": [info.tile_m, info.tile_n]},
+        "roofline": {"bound": "mfma", "achieved": int8_tops, "peak": INT8_PEAK_TOPS,
+                     "unit": "TFLOP/s", "frac": int8_tops / INT8_PEAK_TOPS, "traffic": None,
+                     "kernel": "k_gemm_limb", "kernel_ms": gemm_avg,
+                     "note": "int8 ops (L^2 * 2mnk) per launch / launch time"},
+        "pack_ms": pack_ms / max(pack_n, 1),
+        "plain": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

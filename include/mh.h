@@ -1,0 +1,233 @@
+/*
+ * mh.h -- Morton-hybrid modular matrix multiplication on AMD MI355X (gfx950).
+ *
+ * The operation (Abu Salem and Al Arab, "Cache-oblivious Matrix
+ * Multiplication for Exact Factorisation", section 2): a product of
+ * rectangular sub-matrices of Morton-hybrid parents over the prime field
+ * F_p, in accumulating form (section 2.2):
+ *
+ *     C[rc+i][cc+j] := (C[rc+i][cc+j] + sum_{l<k} A[ra+i][ca+l] * B[rb+l][cb+j]) mod p
+ *
+ * for 0 <= i < m, 0 <= j < n.  The paper names the output A and the factors
+ * B, C; this library names the output C and the factors A (m x k) and
+ * B (k x n).
+ *
+ * Morton-hybrid layout (section 1; section 2.2 Step 1; Prop. 2.5).  An
+ * N x N parent, N = T * 2^q, is cut into T x T tiles.  Tiles are stored in
+ * Z (Morton) order, quadrants NW, NE, SW, SE (row bit more significant);
+ * each tile is T*T contiguous words in row-major order.  Entry (i,j) sits at
+ *     z(i,j) = Z(i/T, j/T) * T^2 + (i mod T) * T + (j mod T),
+ *     Z(I,J) = sum_b (2*I_b + J_b) * 4^b.
+ * The index does not depend on N.  Supported T: 16, 32, 64, 128.
+ *
+ * Conventions for every call below.
+ *  - Matrix pointers are device pointers to uint32 words owned by the
+ *    caller.  Entries must be residues in [0,p); this is not checked.
+ *  - Arguments are validated synchronously before anything is enqueued; a
+ *    call that returns an error has no effect.
+ *  - Device calls are asynchronous on the caller's `stream` (0 = the null
+ *    stream) and return without synchronising.  Faults detected later are
+ *    reported by mh_ctx_last_device_error.
+ *  - A context is used by one host thread at a time.  It owns all device
+ *    workspace (limb panels, task queues, captured graphs); nothing the
+ *    library allocates is visible to the caller.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef MH_H
+#define MH_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mh_ctx mh_ctx;
+
+typedef enum {
+    MH_OK = 0,
+    MH_E_INVALID = 1,      /* null pointer, negative size, bad flag */
+    MH_E_SHAPE = 2,        /* parent size N is not T * 2^q */
+    MH_E_BOUNDS = 3,       /* a block reaches outside its parent */
+    MH_E_MODULUS = 4,      /* p outside [2, 2^31 - 1] */
+    MH_E_ALIAS = 5,        /* an output region overlaps an input region or another output */
+    MH_E_UNSUPPORTED = 6,  /* T not in {16,32,64,128}, or a mode/size the build lacks */
+    MH_E_NOMEM = 7,        /* device or pinned allocation failed */
+    MH_E_DEVICE = 8        /* a HIP call failed */
+} mh_status;
+
+/* Flags of mh_classify_submatrix.  Scattered == !MH_CONTAINED. */
+enum {
+    MH_ALIGNED = 1u,   /* Def. "aligned" (section 2): starts at the first entry of a
+                          T x T tile and is 2^a T x 2^b T (a, b >= 0) */
+    MH_CONTAINED = 2u, /* Def. "contained" (section 2.1): lies inside one T x T tile */
+    MH_QUADRANT = 4u   /* one of the blocks of the quadrant recursion of section 2.2
+                          Step 1 (the parent or a quadrant of one): rows = cols = 2^a T
+                          and row, col multiples of rows; its entries are the index
+                          range [alpha, alpha + lambda) */
+};
+
+/* Arithmetic forms of the product.  All are exact; they differ in speed. */
+enum {
+    MH_MODE_AUTO = 0,      /* pick by shape */
+    MH_MODE_PLAIN_U32 = 1, /* VALU kernel, 64-bit multiply-accumulate with carry word */
+    MH_MODE_LIMB_I8 = 2    /* residues split into signed 8-bit limbs; int8 MFMA with
+                              int32 accumulators; mod-p reduction once per k-block */
+};
+
+/* Kernel classes reported by mh_ctx_kernel_time. */
+enum {
+    MH_K_LAYOUT_FROM = 0,
+    MH_K_LAYOUT_TO = 1,
+    MH_K_PACK = 2,         /* operand packing (limb split or u32 panel copy) */
+    MH_K_GEMM_PLAIN = 3,
+    MH_K_GEMM_LIMB = 4,
+    MH_K_BATCHED_PACK = 5,
+    MH_K_BATCHED_GEMM = 6,
+    MH_K_COUNT = 7
+};
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context bound to HIP device `hip_device`.  *out is set on success.
+ * Errors: MH_E_INVALID (out null), MH_E_DEVICE (no such device). */
+mh_status mh_ctx_create(mh_ctx **out, int hip_device);
+
+/* Synchronise the context's pending work, free its workspace and graphs. */
+mh_status mh_ctx_destroy(mh_ctx *ctx);
+
+/* Static text for a status code (never null). */
+const char *mh_status_string(mh_status s);
+
+/* First asynchronous HIP error seen by the context since the last call
+ * (sticky until read, then cleared).  Queries the device without blocking. */
+mh_status mh_ctx_last_device_error(mh_ctx *ctx);
+
+/* Enable (1) or disable (0) timing: when on, every library kernel launch is
+ * bracketed by HIP events recorded on the stream it is launched on. */
+mh_status mh_ctx_set_timing(mh_ctx *ctx, int enable);
+
+/* Sum of the recorded durations (ms) and the number of launches of kernel
+ * class `kernel` (MH_K_*) since the last reset.  Blocks until the recorded
+ * events have completed.  reset != 0 clears the record afterwards. */
+mh_status mh_ctx_kernel_time(mh_ctx *ctx, int kernel, double *total_ms, int64_t *launches,
+                             int reset);
+
+/* ------------------------------------------------------ host index math */
+
+/* Morton-hybrid index of Cartesian (i,j) for tile edge T (a power of two);
+ * i, j < 2^31.  The paper's encode (section 2.2 Step 2). */
+uint64_t mh_encode(uint64_t i, uint64_t j, uint32_t T);
+
+/* Inverse of mh_encode: the paper's extract_i and extract_j. */
+void mh_extract(uint64_t z, uint32_t T, uint64_t *i, uint64_t *j);
+
+/* Flags (MH_ALIGNED | MH_CONTAINED | MH_QUADRANT) of the rows x cols block
+ * whose first entry is (row, col) in an N x N parent with tile edge T.
+ * O(1), host only.  Errors: MH_E_UNSUPPORTED (T), MH_E_SHAPE (N),
+ * MH_E_INVALID (rows or cols < 1, flags_out null), MH_E_BOUNDS. */
+mh_status mh_classify_submatrix(int64_t N, int32_t T, int64_t row, int64_t col, int64_t rows,
+                                int64_t cols, uint32_t *flags_out);
+
+/* ---------------------------------------------------------------- layout */
+
+/* dst_mh (N*N words, Morton-hybrid) <- src (Cartesian row-major, row length
+ * ld_src >= N).  Both device pointers; they must not overlap. */
+mh_status mh_layout_from_cartesian(mh_ctx *ctx, uint32_t *dst_mh, const uint32_t *src,
+                                   int64_t ld_src, int64_t N, int32_t T, hipStream_t stream);
+
+/* dst (Cartesian row-major, row length ld_dst >= N) <- src_mh (N*N words). */
+mh_status mh_layout_to_cartesian(mh_ctx *ctx, uint32_t *dst, int64_t ld_dst,
+                                 const uint32_t *src_mh, int64_t N, int32_t T,
+                                 hipStream_t stream);
+
+/* --------------------------------------------------------------- product */
+
+/*
+ * C[rc:rc+m, cc:cc+n] := (C + A[ra:ra+m, ca:ca+k] . B[rb:rb+k, cb:cb+n]) mod p
+ * on Morton-hybrid parents C (NC x NC), A (NA x NA), B (NB x NB), all with
+ * tile edge T.  Blocks may be aligned, contained or scattered.  k = 0 leaves
+ * C unchanged; m = 0 or n = 0 is a no-op.  A, B and C may be the same
+ * buffer provided the C block overlaps neither the A nor the B block (the
+ * Schur update of a TU step writes one block of a matrix from two others).
+ * The result is canonical (in [0,p)) and identical for every mode.
+ * Errors: MH_E_INVALID, MH_E_SHAPE, MH_E_BOUNDS, MH_E_MODULUS (p outside
+ * [2, 2^31-1]), MH_E_ALIAS, MH_E_UNSUPPORTED, MH_E_NOMEM.
+ */
+mh_status mh_matmul_modp(mh_ctx *ctx, uint32_t *C, int64_t NC, int64_t rc, int64_t cc,
+                         const uint32_t *A, int64_t NA, int64_t ra, int64_t ca,
+                         const uint32_t *B, int64_t NB, int64_t rb, int64_t cb, int64_t m,
+                         int64_t k, int64_t n, uint32_t p, int32_t T, int32_t mode,
+                         hipStream_t stream);
+
+/* One independent product of a batch (same meaning as mh_matmul_modp). */
+typedef struct {
+    uint32_t *C;
+    const uint32_t *A, *B;
+    int64_t NC, NA, NB;
+    int64_t rc, cc, ra, ca, rb, cb;
+    int64_t m, k, n;
+} mh_mm_desc;
+
+/*
+ * `count` independent products sharing p and T, run as one persistent
+ * launch over a device task queue (section 2.2, Prop. 2.6: the calls of one
+ * recursion level are independent).  descs is a host array.  No two C
+ * blocks may overlap (MH_E_ALIAS); A and B blocks may be shared.  The
+ * launch sequence is captured once into a HIP graph per context and
+ * replayed; only the queue contents change between calls.  mode selects
+ * the arithmetic form (MH_MODE_AUTO and MH_MODE_LIMB_I8 use limbs).
+ */
+mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *descs, int32_t count,
+                                 uint32_t p, int32_t T, int32_t mode, hipStream_t stream);
+
+/* ------------------------------------------------------ planner, host only */
+
+/* What the planner makes of one product (no device work, no validation of
+ * pointers; sizes and bounds are validated as for mh_matmul_modp). */
+typedef struct {
+    int64_t row_segments;   /* segments of [0,m) cut by C's and A's tile rows */
+    int64_t inner_segments; /* segments of [0,k) cut by A's tile columns and B's tile rows */
+    int64_t col_segments;   /* segments of [0,n) cut by C's and B's tile columns */
+    int64_t leaves;         /* base cases of the section 2.2 recursion: the product of the three */
+    int64_t c_tiles;        /* C tiles the output block touches (each written by one task) */
+    int64_t gemm_tasks;     /* output blocks handed to workgroups */
+    int64_t pack_chunks;    /* operand chunks handed to the packing kernel (0 if none) */
+    int32_t mode;           /* mode the call would run in */
+    int32_t in_place;       /* 1 if the plain kernel reads A and B tiles in place */
+    int32_t tile_m, tile_n; /* output block of one workgroup */
+    int32_t limbs;          /* limbs per residue (limb mode) */
+    int32_t kblock;         /* k-block length between reductions mod p (limb mode) */
+} mh_plan_info;
+
+mh_status mh_plan_describe(int64_t NC, int64_t rc, int64_t cc, int64_t NA, int64_t ra,
+                           int64_t ca, int64_t NB, int64_t rb, int64_t cb, int64_t m,
+                           int64_t k, int64_t n, uint32_t p, int32_t T, int32_t mode,
+                           mh_plan_info *out);
+
+/*
+ * The leaves themselves: box q is out[6q..6q+5] = (i0, ni, l0, nl, j0, nj)
+ * in product coordinates; C piece rows [i0,i0+ni) x cols [j0,j0+nj), A piece
+ * [i0..) x [l0..), B piece [l0..) x [j0..).  Every piece lies in one tile.
+ * Writes at most `cap` boxes and sets *count to the total.
+ */
+mh_status mh_plan_leaves(int64_t NC, int64_t rc, int64_t cc, int64_t NA, int64_t ra,
+                         int64_t ca, int64_t NB, int64_t rb, int64_t cb, int64_t m, int64_t k,
+                         int64_t n, int32_t T, int64_t *out, int64_t cap, int64_t *count);
+
+/*
+ * The output blocks of the workgroups: task q is out[4q..4q+3] =
+ * (i0, ni, j0, nj) in product coordinates.  They partition [0,m) x [0,n)
+ * and each lies inside C tiles it writes whole (clipped to the block).
+ */
+mh_status mh_plan_gemm_tasks(int64_t NC, int64_t rc, int64_t cc, int64_t NA, int64_t ra,
+                             int64_t ca, int64_t NB, int64_t rb, int64_t cb, int64_t m,
+                             int64_t k, int64_t n, uint32_t p, int32_t T, int32_t mode,
+                             int64_t *out, int64_t cap, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MH_H */

@@ -1,0 +1,58 @@
+// The context object behind the opaque mh_ctx handle, and host helpers
+// shared by the host runtime files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <vector>
+
+#include "mh_internal.h"
+
+namespace mh {
+
+struct TimedLaunch {
+    hipEvent_t a, b;
+    int kernel;
+};
+
+// State of the batched path (persistent kernels, queue, graph).
+struct BatchedState {
+    void *queue_dev = nullptr;       // device copy of the task queue
+    size_t queue_cap = 0;
+    void *queue_host = nullptr;      // pinned staging buffer
+    size_t queue_host_cap = 0;
+    hipEvent_t staging_free = nullptr;  // recorded after the H2D copy of the last call
+    int *counters = nullptr;         // device work counters
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_key = -1;              // kernel configuration the graph was captured for
+    void *graph_queue = nullptr;     // queue address baked into the graph
+};
+
+struct DeviceGuard {
+    int prev;
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+};
+
+mh_status note_error(mh_ctx *ctx, hipError_t e);
+void record_start(mh_ctx *ctx, int kernel, hipStream_t s, TimedLaunch &t);
+void record_end(mh_ctx *ctx, hipStream_t s, TimedLaunch &t);
+void *workspace(mh_ctx *ctx, size_t bytes);
+bool outputs_alias(const Product &x, const Product &y);
+void batched_release(mh_ctx *ctx);
+
+}  // namespace mh
+
+struct mh_ctx {
+    int device = 0;
+    int num_cu = 256;
+    void *ws = nullptr;
+    size_t ws_size = 0;
+    bool timing = false;
+    std::vector<mh::TimedLaunch> records;
+    std::vector<hipEvent_t> event_pool;
+    mh_status sticky = MH_OK;
+    mh::BatchedState batched;
+};

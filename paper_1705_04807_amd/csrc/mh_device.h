@@ -1,0 +1,60 @@
+// Device helpers shared by the HIP kernels of libmh.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "mh_internal.h"
+
+namespace mh {
+
+// Calls f(std::integral_constant<int, 0>{}) ... f(<N-1>): a loop whose index
+// is a compile-time constant in the body, independent of the unroller.
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// x mod p for any 64-bit x, by Barrett reduction (Barrett, CRYPTO 1986)
+// with mu = floor((2^64 - 1) / p): the estimated quotient is at most two
+// below the true one, so at most two corrections follow.
+__device__ __forceinline__ uint32_t mod_u64(uint64_t x, uint32_t p, uint64_t mu)
+{
+    uint64_t q = __umul64hi(x, mu);
+    uint64_t r = x - q * p;
+    if (r >= p) r -= p;
+    if (r >= p) r -= p;
+    return uint32_t(r);
+}
+
+// Workgroup id -> output tile (gm, gn).  Workgroups are dispatched to the
+// 8 XCDs round-robin; the first step gives each XCD a contiguous range of
+// logical tile ids so that the workgroups sharing one XCD's L2 also share
+// operand panels.  The second walks the tiles in groups of `group_m` tile
+// rows, column by column, so concurrently running tiles reuse A slabs.
+__device__ __forceinline__ void tile_of(int64_t bid, int64_t grid_m, int64_t grid_n, int group_m,
+                                        int64_t &gm, int64_t &gn)
+{
+    const int64_t G = grid_m * grid_n;
+    const int64_t per = G / 8, rem = G % 8;
+    const int64_t x = bid % 8, idx = bid / 8;
+    int64_t lid = (x < rem) ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+    const int64_t width = int64_t(group_m) * grid_n;
+    const int64_t g = lid / width;
+    const int64_t first = g * group_m;
+    const int64_t gsz = (grid_m - first) < group_m ? (grid_m - first) : group_m;
+    const int64_t in = lid - g * width;
+    gm = first + in % gsz;
+    gn = in / gsz;
+}
+
+}  // namespace mh

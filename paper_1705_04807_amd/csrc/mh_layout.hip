@@ -1,0 +1,91 @@
+// Layout conversion kernels: Cartesian row-major <-> Morton-hybrid.
+//
+// One workgroup converts whole tiles.  The Morton-hybrid side of a tile is
+// T*T contiguous words (section 1; Prop. 2.5 row-major tiles), so it is read
+// or written as one contiguous run; the Cartesian side is T row segments of
+// T words.  The tile coordinates come from de-interleaving the tile's Z
+// index once per tile, never per element.  HBM-bound: 4 bytes read and
+// 4 bytes written per word.
+#include "mh_internal.h"
+
+namespace mh {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// Tiles handled by one workgroup: at least 4096 words per group.
+__host__ __device__ constexpr int tiles_per_group(int logT)
+{
+    return (2 * logT >= 12) ? 1 : (1 << (12 - 2 * logT));
+}
+
+template <bool TO_MH, bool VEC>
+__global__ __launch_bounds__(kThreads) void k_layout(uint32_t *__restrict__ dst,
+                                                     const uint32_t *__restrict__ src,
+                                                     int64_t ld, int logT, uint64_t ntiles)
+{
+    const int T = 1 << logT;
+    const int tpg = tiles_per_group(logT);
+    const uint64_t tile0 = uint64_t(blockIdx.x) * tpg;
+    const int words = T << logT;                 // per tile
+    const int per_group = tpg * words;
+    constexpr int W = VEC ? 4 : 1;
+    for (int e = threadIdx.x * W; e < per_group; e += kThreads * W) {
+        const uint64_t tz = tile0 + (e >> (2 * logT));
+        if (tz >= ntiles) break;
+        const int r = (e >> logT) & (T - 1);
+        const int c = e & (T - 1);
+        const uint64_t I = compact32(tz >> 1), J = compact32(tz);
+        const uint64_t cart = ((I << logT) + r) * uint64_t(ld) + (J << logT) + c;
+        const uint64_t mh = (tz << (2 * logT)) + (uint64_t(r) << logT) + c;
+        if (VEC) {
+            if (TO_MH) {
+                uint4 v = *reinterpret_cast<const uint4 *>(src + cart);
+                *reinterpret_cast<uint4 *>(dst + mh) = v;
+            } else {
+                uint4 v = *reinterpret_cast<const uint4 *>(src + mh);
+                *reinterpret_cast<uint4 *>(dst + cart) = v;
+            }
+        } else {
+            if (TO_MH)
+                dst[mh] = src[cart];
+            else
+                dst[cart] = src[mh];
+        }
+    }
+}
+
+template <bool TO_MH>
+hipError_t launch(uint32_t *dst, const uint32_t *src, int64_t ld, int64_t N, int logT,
+                  hipStream_t s)
+{
+    const uint64_t q = uint64_t(N) >> logT;
+    const uint64_t ntiles = q * q;
+    const int tpg = tiles_per_group(logT);
+    const uint64_t groups = (ntiles + tpg - 1) / tpg;
+    const bool vec = (ld % 4 == 0) && ((uintptr_t)src % 16 == 0) && ((uintptr_t)dst % 16 == 0);
+    if (vec)
+        hipLaunchKernelGGL((k_layout<TO_MH, true>), dim3(unsigned(groups)), dim3(kThreads), 0, s,
+                           dst, src, ld, logT, ntiles);
+    else
+        hipLaunchKernelGGL((k_layout<TO_MH, false>), dim3(unsigned(groups)), dim3(kThreads), 0, s,
+                           dst, src, ld, logT, ntiles);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_layout_from(uint32_t *dst, const uint32_t *src, int64_t ld, int64_t N, int logT,
+                              hipStream_t s)
+{
+    return launch<true>(dst, src, ld, N, logT, s);
+}
+
+hipError_t launch_layout_to(uint32_t *dst, int64_t ld, const uint32_t *src, int64_t N, int logT,
+                            hipStream_t s)
+{
+    return launch<false>(dst, src, ld, N, logT, s);
+}
+
+}  // namespace mh

@@ -1,0 +1,197 @@
+// Operand packing kernels.
+//
+// A non-aligned operand block is copied once into a panel whose tiles line
+// up with the output's tile grid, so that the GEMM kernels afterwards only
+// read contiguous, aligned data (the section 2.1 locality argument: base
+// cases should read row-major pieces, never per-element Morton-hybrid
+// encodes).  Within the source, every row segment of a tile is contiguous;
+// the Morton-hybrid address of an element is split into a row part and a
+// column part, so one encode is shared by a whole row or column of the
+// workgroup's chunk.
+//
+// pack_u32:  tile-major uint32 panel for the plain kernel.
+// pack_limb: signed 8-bit limb planes in MFMA operand order for the int8
+//            MFMA kernel (balanced base-256 digits of the centred residue).
+#include "mh_device.h"
+
+namespace mh {
+
+namespace {
+
+__device__ __forceinline__ uint64_t row_part(uint64_t r, int logT)
+{
+    return (uint64_t(spread16(uint32_t(r >> logT))) << (2 * logT + 1)) |
+           ((r & ((1u << logT) - 1)) << logT);
+}
+
+__device__ __forceinline__ uint64_t col_part(uint64_t c, int logT)
+{
+    return (uint64_t(spread16(uint32_t(c >> logT))) << (2 * logT)) | (c & ((1u << logT) - 1));
+}
+
+// ------------------------------------------------------------ u32 panel
+
+// Panel of prow x pcol words in T x T tiles, tile-major: tile (tr, tc) at
+// dst + (tr * pcol/T + tc) * T^2.  Panel entry (r, c) holds source entry
+// (srow0 + r, scol0 + c) when r in [vr0, vr1) and c in [vc0, vc1), else 0.
+// One workgroup per tile.
+__global__ __launch_bounds__(256) void k_pack_u32(uint32_t *__restrict__ dst, int64_t ntc,
+                                                  const uint32_t *__restrict__ src, int64_t srow0,
+                                                  int64_t scol0, int64_t vr0, int64_t vr1,
+                                                  int64_t vc0, int64_t vc1, int logT)
+{
+    const int T = 1 << logT;
+    const int64_t tr = blockIdx.y, tc = blockIdx.x;
+    uint32_t *out = dst + (tr * ntc + tc) * (int64_t(T) << logT);
+    for (int e = threadIdx.x; e < (T << logT); e += 256) {
+        const int64_t r = (tr << logT) + (e >> logT);
+        const int64_t c = (tc << logT) + (e & (T - 1));
+        uint32_t v = 0;
+        if (r >= vr0 && r < vr1 && c >= vc0 && c < vc1)
+            v = src[row_part(uint64_t(srow0 + r), logT) | col_part(uint64_t(scol0 + c), logT)];
+        out[e] = v;
+    }
+}
+
+// ------------------------------------------------------------ limb panel
+
+constexpr int kChunk = 64;         // panel rows x depth per workgroup
+constexpr int kLdsStride = 68;     // words per LDS row (padding against bank conflicts)
+
+template <int L>
+__device__ __forceinline__ void digits16(const uint32_t *x, uint32_t p, int32_t H, uint4 *out)
+{
+    // out[t] holds digit t of the 16 residues, one byte each (element e in
+    // byte e%4 of word e/4).
+    uint32_t w[L][4];
+#pragma unroll
+    for (int t = 0; t < L; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[t][q] = 0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        int32_t v = int32_t(x[e]);
+        v = v > H ? v - int32_t(p) : v;  // centred residue
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+            const int32_t d = int32_t(int8_t(v & 0xFF));  // balanced digit in [-128, 127]
+            w[t][e >> 2] |= (uint32_t(d) & 0xFFu) << (8 * (e & 3));
+            v = (v - d) >> 8;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < L; ++t) out[t] = make_uint4(w[t][0], w[t][1], w[t][2], w[t][3]);
+}
+
+// Limb panel layout: 32-row slabs x 32-deep k-blocks x L limbs, 1 KiB per
+// (slab, kb, limb); lane q of a block holds row (q & 31), depth
+// (q >> 5) * 16 .. +15.  One workgroup packs 64 panel rows x 64 depth
+// (2 slabs x 2 k-blocks).  trans = 0: panel (rho, kap) <- src(r0 + rho -
+// shift, c0 + kap); trans = 1: src(r0 + kap, c0 + rho - shift).  Entries
+// with rho outside [shift, shift + R) or kap >= K are zero.
+template <int L, bool TRANS>
+__global__ __launch_bounds__(256) void k_pack_limb(int8_t *__restrict__ dst, int64_t nkb,
+                                                   const uint32_t *__restrict__ src, int64_t r0,
+                                                   int64_t c0, int64_t shift, int64_t R, int64_t K,
+                                                   int logT, uint32_t p, int32_t H)
+{
+    __shared__ uint32_t tile[kChunk * kLdsStride];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t rho0 = int64_t(blockIdx.y) * kChunk;
+    const int64_t kap0 = int64_t(blockIdx.x) * kChunk;
+
+    if (!TRANS) {
+        // lanes walk the depth (source columns, contiguous inside a tile row)
+        const int64_t kap = kap0 + lane;
+        const bool kok = kap < K;
+        const uint64_t cpart = col_part(uint64_t(c0 + kap), logT);
+#pragma unroll 4
+        for (int i = 0; i < kChunk / 4; ++i) {
+            const int rr = wave + 4 * i;
+            const int64_t rho = rho0 + rr;
+            uint32_t v = 0;
+            if (kok && rho >= shift && rho < shift + R)
+                v = src[row_part(uint64_t(r0 + rho - shift), logT) | cpart];
+            tile[rr * kLdsStride + lane] = v;
+        }
+    } else {
+        // lanes walk the panel rows (source columns, contiguous inside a tile row)
+        const int64_t rho = rho0 + lane;
+        const bool rok = rho >= shift && rho < shift + R;
+        const uint64_t cpart = col_part(uint64_t(c0 + rho - shift), logT);
+#pragma unroll 4
+        for (int i = 0; i < kChunk / 4; ++i) {
+            const int kk = wave + 4 * i;
+            const int64_t kap = kap0 + kk;
+            uint32_t v = 0;
+            if (rok && kap < K) v = src[row_part(uint64_t(r0 + kap), logT) | cpart];
+            tile[lane * kLdsStride + kk] = v;
+        }
+    }
+    __syncthreads();
+
+    const int sl = wave >> 1, kbl = wave & 1;
+    const int64_t kb = kap0 / 32 + kbl;
+    if (kb >= nkb) return;
+    const int rr = sl * 32 + (lane & 31);
+    const int kk = kbl * 32 + (lane >> 5) * 16;
+    uint32_t x[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(&tile[rr * kLdsStride + kk + 4 * q]);
+        x[4 * q] = v.x;
+        x[4 * q + 1] = v.y;
+        x[4 * q + 2] = v.z;
+        x[4 * q + 3] = v.w;
+    }
+    uint4 d[L];
+    digits16<L>(x, p, H, d);
+    const int64_t slab = rho0 / 32 + sl;
+    uint4 *o = reinterpret_cast<uint4 *>(dst + ((slab * nkb + kb) * L) * 1024) + lane;
+#pragma unroll
+    for (int t = 0; t < L; ++t) o[t * 64] = d[t];
+}
+
+template <int L>
+hipError_t launch_limb_L(int8_t *dst, int64_t prow, int64_t nkb, const uint32_t *src, int64_t r0,
+                         int64_t c0, int64_t shift, int64_t R, int64_t K, int trans, int logT,
+                         uint32_t p, hipStream_t s)
+{
+    const int32_t H = int32_t(limb_threshold(L));
+    dim3 grid(unsigned((nkb + 1) / 2), unsigned(prow / kChunk));
+    if (trans)
+        hipLaunchKernelGGL((k_pack_limb<L, true>), grid, dim3(256), 0, s, dst, nkb, src, r0, c0,
+                           shift, R, K, logT, p, H);
+    else
+        hipLaunchKernelGGL((k_pack_limb<L, false>), grid, dim3(256), 0, s, dst, nkb, src, r0, c0,
+                           shift, R, K, logT, p, H);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_pack_u32(uint32_t *dst, int64_t prow, int64_t pcol, const uint32_t *src,
+                           int64_t srow0, int64_t scol0, int64_t vr0, int64_t vr1, int64_t vc0,
+                           int64_t vc1, int logT, hipStream_t s)
+{
+    const int64_t ntr = prow >> logT, ntc = pcol >> logT;
+    if (ntr <= 0 || ntc <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_u32, dim3(unsigned(ntc), unsigned(ntr)), dim3(256), 0, s, dst, ntc,
+                       src, srow0, scol0, vr0, vr1, vc0, vc1, logT);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_limb(int8_t *dst, int64_t prow, int64_t nkb, const uint32_t *src,
+                            int64_t r0, int64_t c0, int64_t shift, int64_t R, int64_t K, int trans,
+                            int logT, uint32_t p, int L, hipStream_t s)
+{
+    if (prow <= 0 || nkb <= 0) return hipSuccess;
+    switch (L) {
+    case 1: return launch_limb_L<1>(dst, prow, nkb, src, r0, c0, shift, R, K, trans, logT, p, s);
+    case 2: return launch_limb_L<2>(dst, prow, nkb, src, r0, c0, shift, R, K, trans, logT, p, s);
+    case 3: return launch_limb_L<3>(dst, prow, nkb, src, r0, c0, shift, R, K, trans, logT, p, s);
+    default: return launch_limb_L<4>(dst, prow, nkb, src, r0, c0, shift, R, K, trans, logT, p, s);
+    }
+}
+
+}  // namespace mh
