@@ -80,6 +80,15 @@ class mh_plan_info(ct.Structure):
 
 
 def _load():
+    # One HIP runtime per process: torch ships its own libamdhip64 and
+    # libhsa-runtime64 (same sonames as ROCm's).  Loading torch first makes
+    # libmh bind to those copies, so device pointers and streams from torch
+    # are valid in libmh; loading libmh first would bring in a second runtime
+    # that cannot open the device once torch has.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError("libmh.so is not built (run paper_1705_04807_amd/build.py): " + LIB_PATH)
     L = ct.CDLL(LIB_PATH)
