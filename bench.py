@@ -12,13 +12,23 @@ HBM in Morton-hybrid layout.  Prints one JSON line:
              bounded sample of output rows of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+       python bench.py --copy-calibration   (plain 1 GiB device copy, three times:
+                                             the reference for scaling HBM counters)
+
+roofline.traffic comes from the committed rocprofv3 counter summary under
+profiles/ (a "traffic-record:" line); it is used only when that record names
+the same kernel configuration, workload and kernel source hash as this run,
+and is null otherwise.
 """
 
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -42,11 +52,55 @@ WORKLOADS = {
         N=8192, T=64, p=65521, m=6000, k=3000, n=5000,
         off=(64, 33, 1000, 1500, 517, 2048), seeds=(3001, 3002, 3003)),
 }
+# 512 uneven independent products of one TU recursion level, one batched call
+BATCHED = "batched_512_tu_level_8192parents_p65521_T64"
 DEFAULT = "modp_8192cube_p2^31-1_T64"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+KERNEL_SOURCES = ("paper_1705_04807_amd/csrc/mh_gemm_limb.hip",
+                  "paper_1705_04807_amd/csrc/mh_device.h",
+                  "paper_1705_04807_amd/csrc/mh_internal.h")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str, cfg: int, workload: str):
+    """HBM bytes per launch (fetch + write) from a matching traffic-record, else None."""
+    src = kernel_source_hash()
+    pat = re.compile(r"traffic-record:\s+kernel=(\S+)\s+cfg=(\S+)\s+workload=(\S+)\s+src=(\S+)"
+                     r"\s+fetch_bytes=(\d+)\s+write_bytes=(\d+)")
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*"))):
+        try:
+            text = open(path).read()
+        except OSError:
+            continue
+        for m in pat.finditer(text):
+            if (m.group(1), m.group(2), m.group(3), m.group(4)) == (kernel, str(cfg), workload, src):
+                return int(m.group(5)) + int(m.group(6))
+    return None
+
+
+def copy_calibration() -> None:
+    """A plain device copy of 1 GiB, three times (reads 1 GiB, writes 1 GiB each)."""
+    import torch
+    n = 1 << 28
+    src = torch.arange(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_launch": 4 * n}), flush=True)
 
 
 def cpu_threads() -> int:
@@ -93,14 +147,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + [BATCHED])
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X and has no "
               "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == BATCHED:
+        bench_batched(args)
+        return
 
     import torch
 
@@ -201,10 +263,117 @@ def main():
                    "parents": N, "offsets_c_a_b": list(W["off"]), "limbs": L,
                    "mode": "limb_i8", "tile": [info.tile_m, info.tile_n]},
         "roofline": {"bound": "mfma", "achieved": int8_tops, "peak": INT8_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": int8_tops / INT8_PEAK_TOPS, "traffic": None,
-                     "kernel": "k_gemm_limb", "kernel_ms": gemm_avg,
-                     "note": "int8 ops (L^2 * 2mnk) per launch / launch time"},
+                     "unit": "TFLOP/s", "frac": int8_tops / INT8_PEAK_TOPS,
+                     "traffic": recorded_traffic("k_gemm_limb", info.kernel_cfg, args.workload),
+                     "kernel": "k_gemm_limb", "kernel_cfg": info.kernel_cfg,
+                     "kernel_src": kernel_source_hash(), "kernel_ms": gemm_avg,
+                     "note": "achieved = int8 ops (L^2 * 2mnk) per launch / average launch "
+                             "time; traffic = HBM bytes per launch from FETCH_SIZE and "
+                             "WRITE_SIZE, copy-calibrated"},
         "pack_ms": pack_ms / max(pack_n, 1),
+        "plain": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """One step = one mh_matmul_modp_batched call over the 512 products."""
+    import numpy as np
+    import torch
+
+    import paper_1705_04807_amd as mh
+    from seeded_inputs import residues_torch, tu_level_batch
+
+    N, T, p, nC = 8192, 64, 65521, 64
+    calls = tu_level_batch(seed=5000, count=512, N=N, n_c_parents=nC)
+    work = float(sum(2 * c["m"] * c["k"] * c["n"] for c in calls))
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    sh = stream.cuda_stream
+    ctx = mh.mh_ctx_create(0)
+    log("generating %d parents" % (nC + 2))
+
+    def parent(seed):
+        X = residues_torch(seed, p, N, N, device="cuda")
+        Y = torch.empty(N * N, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        mh.check(mh.mh_layout_from_cartesian(ctx, Y.data_ptr(), X.data_ptr(), N, N, T, sh))
+        stream.synchronize()
+        return X, Y
+
+    Acart, A = parent(5001)
+    Bcart, B = parent(5002)
+    Cs = [parent(5100 + j)[1] for j in range(nC)]
+    descs = mh.make_descs([dict(C=Cs[c["ci"]].data_ptr(), A=A.data_ptr(), B=B.data_ptr(),
+                                NC=N, NA=N, NB=N, rc=c["rc"], cc=c["cc"], ra=c["ra"],
+                                ca=c["ca"], rb=c["rb"], cb=c["cb"], m=c["m"], k=c["k"],
+                                n=c["n"]) for c in calls])
+
+    def batched(mode):
+        mh.check(mh.mh_matmul_modp_batched(ctx, descs, len(calls), p, T, mode, sh), "batched")
+
+    def looped(mode):
+        for c in calls:
+            mh.check(mh.mh_matmul_modp(ctx, Cs[c["ci"]].data_ptr(), N, c["rc"], c["cc"],
+                                       A.data_ptr(), N, c["ra"], c["ca"], B.data_ptr(), N,
+                                       c["rb"], c["cb"], c["m"], c["k"], c["n"], p, T, mode, sh))
+
+    def timed(fn, steps, kernels=()):
+        stream.synchronize()
+        mh.mh_ctx_set_timing(ctx, True)
+        for kk in range(mh.MH_K_COUNT):
+            mh.mh_ctx_kernel_time(ctx, kk, reset=True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        stream.synchronize()
+        el = time.perf_counter() - t0
+        ks = {kk: mh.mh_ctx_kernel_time(ctx, kk, reset=True) for kk in kernels}
+        mh.mh_ctx_set_timing(ctx, False)
+        return el / steps, ks
+
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        batched(mh.MH_MODE_LIMB_I8)
+    t_b, ks = timed(lambda: batched(mh.MH_MODE_LIMB_I8), args.steps, (mh.MH_K_BATCHED,))
+    graph_ms = ks[mh.MH_K_BATCHED][0] / max(ks[mh.MH_K_BATCHED][1], 1)
+    value = work / t_b / 1e9
+    log("batched: %.3f ms/step (graph %.3f ms)" % (t_b * 1e3, graph_ms))
+    looped(mh.MH_MODE_LIMB_I8)
+    t_l, _ = timed(lambda: looped(mh.MH_MODE_LIMB_I8), 1)
+    log("looped: %.3f ms" % (t_l * 1e3))
+    plain = None
+    if args.plain_steps > 0:
+        t_p, _ = timed(lambda: batched(mh.MH_MODE_PLAIN_U32), 1)
+        plain = {"value": work / t_p / 1e9, "unit": "GOPS", "ms_per_step": t_p * 1e3,
+                 "limb_speedup": value / (work / t_p / 1e9)}
+        log("plain: %.3f ms" % (t_p * 1e3))
+    assert mh.mh_ctx_last_device_error(ctx) == 0
+    L = 2
+    int8_tops = L * L * work / (graph_ms * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        c0 = max(calls, key=lambda c: c["m"] * c["n"] * c["k"])
+        W = dict(p=p, m=c0["m"], k=c0["k"], n=c0["n"],
+                 off=(c0["rc"], c0["cc"], c0["ra"], c0["ca"], c0["rb"], c0["cb"]))
+        cpu = cpu_baseline(Acart.view(N, N), Bcart.view(N, N), W)
+        cpu["sample"] = "largest product of the batch: " + cpu["sample"]
+    mh.mh_ctx_destroy(ctx)
+    out = {
+        "metric": METRIC, "value": value, "unit": "GOPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_b * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+        "config": {"workload": BATCHED, "products": len(calls), "work_2mnk": work, "p": p,
+                   "T": T, "parents": N, "c_parents": nC, "limbs": L, "mode": "limb_i8",
+                   "form": "persistent pack + GEMM in one HIP graph"},
+        "roofline": {"bound": "mfma", "achieved": int8_tops, "peak": INT8_PEAK_TOPS,
+                     "unit": "TFLOP/s", "frac": int8_tops / INT8_PEAK_TOPS, "traffic": None,
+                     "kernel": "batched graph (k_pack_limb_batched + k_gemm_limb_batched)",
+                     "kernel_ms": graph_ms,
+                     "note": "achieved = int8 ops of the whole batch / graph time"},
+        "looped": {"value": work / t_l / 1e9, "unit": "GOPS", "ms_per_step": t_l * 1e3},
         "plain": plain,
         "cpu_baseline": cpu,
     }

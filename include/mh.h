@@ -83,9 +83,8 @@ enum {
     MH_K_PACK = 2,         /* operand packing (limb split or u32 panel copy) */
     MH_K_GEMM_PLAIN = 3,
     MH_K_GEMM_LIMB = 4,
-    MH_K_BATCHED_PACK = 5,
-    MH_K_BATCHED_GEMM = 6,
-    MH_K_COUNT = 7
+    MH_K_BATCHED = 5,      /* one batched graph: persistent pack + persistent GEMM */
+    MH_K_COUNT = 6
 };
 
 /* ---------------------------------------------------------------- context */
@@ -173,11 +172,16 @@ typedef struct {
 /*
  * `count` independent products sharing p and T, run as one persistent
  * launch over a device task queue (section 2.2, Prop. 2.6: the calls of one
- * recursion level are independent).  descs is a host array.  No two C
- * blocks may overlap (MH_E_ALIAS); A and B blocks may be shared.  The
- * launch sequence is captured once into a HIP graph per context and
- * replayed; only the queue contents change between calls.  mode selects
- * the arithmetic form (MH_MODE_AUTO and MH_MODE_LIMB_I8 use limbs).
+ * recursion level are independent).  descs is a host array.  No C block may
+ * overlap another C block or any A or B block of the batch (MH_E_ALIAS); A
+ * and B blocks may be shared.  The launch sequence (counter reset,
+ * persistent packing kernel, persistent GEMM kernel) is captured once into a
+ * HIP graph per context and replayed; only the queue contents change
+ * between calls, through one host-to-device copy on `stream`.  Consecutive
+ * batched calls of one context must be ordered (same stream or
+ * synchronised), since they share the queue and the workspace.  mode:
+ * MH_MODE_AUTO and MH_MODE_LIMB_I8 run the limb form; MH_MODE_PLAIN_U32 runs
+ * the products one after another with the plain kernel.
  */
 mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *descs, int32_t count,
                                  uint32_t p, int32_t T, int32_t mode, hipStream_t stream);
@@ -199,6 +203,7 @@ typedef struct {
     int32_t tile_m, tile_n; /* output block of one workgroup */
     int32_t limbs;          /* limbs per residue (limb mode) */
     int32_t kblock;         /* k-block length between reductions mod p (limb mode) */
+    int32_t kernel_cfg;     /* limb GEMM configuration the call would launch (-1: none) */
 } mh_plan_info;
 
 mh_status mh_plan_describe(int64_t NC, int64_t rc, int64_t cc, int64_t NA, int64_t ra,

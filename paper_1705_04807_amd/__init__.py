@@ -43,9 +43,8 @@ MH_K_LAYOUT_TO = 1
 MH_K_PACK = 2
 MH_K_GEMM_PLAIN = 3
 MH_K_GEMM_LIMB = 4
-MH_K_BATCHED_PACK = 5
-MH_K_BATCHED_GEMM = 6
-MH_K_COUNT = 7
+MH_K_BATCHED = 5
+MH_K_COUNT = 6
 
 # Every symbol declared in include/mh.h.
 EXPORTS = (
@@ -76,7 +75,7 @@ class mh_plan_info(ct.Structure):
                 ("col_segments", ct.c_int64), ("leaves", ct.c_int64), ("c_tiles", ct.c_int64),
                 ("gemm_tasks", ct.c_int64), ("pack_chunks", ct.c_int64), ("mode", ct.c_int32),
                 ("in_place", ct.c_int32), ("tile_m", ct.c_int32), ("tile_n", ct.c_int32),
-                ("limbs", ct.c_int32), ("kblock", ct.c_int32)]
+                ("limbs", ct.c_int32), ("kblock", ct.c_int32), ("kernel_cfg", ct.c_int32)]
 
 
 def _load():

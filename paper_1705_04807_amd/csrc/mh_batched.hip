@@ -1,10 +1,170 @@
-// Batched products (placeholder: one product after another).
+// Batched products: one persistent launch over a device task queue,
+// captured once into a HIP graph and replayed.
+//
+// The calls of one recursion level of a TU factorisation are independent
+// (section 2.2, Prop. 2.6: the recursive calls can be cast in parallel), so
+// a whole batch runs as
+//   reset counters -> persistent pack kernel -> persistent GEMM kernel
+// on one stream.  Each persistent kernel has a fixed grid (CUs x occupancy)
+// and pops work items through an atomic counter until the queue is empty,
+// so the graph's topology never changes: a new batch only rewrites the
+// queue (one host-to-device copy from pinned staging memory) before the
+// graph is launched again.  Products are queued largest k first, so the
+// longest output blocks start first (longest-processing-time order).
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
 #include "mh_ctx.h"
 #include "mh_device.h"
 
 namespace mh {
 
-void batched_release(mh_ctx *ctx) { (void)ctx; }
+namespace {
+
+__global__ void k_reset_counters(uint64_t *c)
+{
+    if (threadIdx.x < 2) c[threadIdx.x] = 0;
+}
+
+int batch_cfg(int L, const std::vector<Plan> &plans)
+{
+    double area = 0.0;
+    for (const Plan &p : plans) area += double(p.pr.m) * double(p.pr.n);
+    area /= std::max<size_t>(plans.size(), 1);
+    int cfg = area <= 512.0 * 512.0 ? 6 : (L <= 2 ? 5 : 4);
+    if (const char *e = std::getenv("MH_LIMB_CFG")) {  // explicit override (tuning runs)
+        int c = std::atoi(e);
+        if (c >= 0 && c < limb_cfg_count() && (2 * L - 1) * limb_cfg(c).wm * limb_cfg(c).wn <= 14)
+            cfg = c;
+    }
+    return cfg;
+}
+
+// Capacity (products) of the queue buffers, reallocating them if needed.
+mh_status ensure_queue(mh_ctx *ctx, int64_t ncalls)
+{
+    BatchedState &b = ctx->batched;
+    if (b.queue_dev && ncalls <= b.queue_cap) return MH_OK;
+    int64_t cap = 64;
+    while (cap < ncalls) cap *= 2;
+    (void)hipDeviceSynchronize();
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+    if (b.queue_dev) (void)hipFree(b.queue_dev);
+    if (b.queue_host) (void)hipHostFree(b.queue_host);
+    b.queue_dev = b.queue_host = nullptr;
+    b.queue_cap = 0;
+    const size_t bytes = queue_bytes(cap);
+    if (hipMalloc(&b.queue_dev, bytes) != hipSuccess) {
+        b.queue_dev = nullptr;
+        (void)hipGetLastError();
+        return MH_E_NOMEM;
+    }
+    if (hipHostMalloc(&b.queue_host, bytes, hipHostMallocDefault) != hipSuccess) {
+        b.queue_host = nullptr;
+        (void)hipGetLastError();
+        return MH_E_NOMEM;
+    }
+    if (!b.counters && hipMalloc((void **)&b.counters, 2 * sizeof(uint64_t)) != hipSuccess) {
+        b.counters = nullptr;
+        (void)hipGetLastError();
+        return MH_E_NOMEM;
+    }
+    if (!b.staging_free && hipEventCreateWithFlags(&b.staging_free, hipEventDisableTiming) !=
+                               hipSuccess) {
+        b.staging_free = nullptr;
+        return MH_E_DEVICE;
+    }
+    if (!b.capture_stream &&
+        hipStreamCreateWithFlags(&b.capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        b.capture_stream = nullptr;
+        return MH_E_DEVICE;
+    }
+    b.queue_cap = cap;
+    b.graph_key = -1;
+    return MH_OK;
+}
+
+// Capture reset -> pack -> GEMM for kernel configuration cfg and L limbs.
+mh_status ensure_graph(mh_ctx *ctx, int cfg, int L)
+{
+    BatchedState &b = ctx->batched;
+    const int key = cfg * 8 + L;
+    if (b.exec && b.graph_key == key) return MH_OK;
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+    const QueueView q = queue_view(b.queue_dev, b.queue_cap);
+    hipStream_t cs = b.capture_stream;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return MH_E_DEVICE;
+    hipError_t e1 = launch_reset_counters(b.counters, cs);
+    hipError_t e2 = launch_pack_limb_batched(L, q, b.counters, ctx->num_cu, cs);
+    hipError_t e3 = launch_gemm_limb_batched(cfg, L, q, b.counters + 1, ctx->num_cu, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e4 = hipStreamEndCapture(cs, &g);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return MH_E_DEVICE;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return MH_E_DEVICE;
+    }
+    b.graph = g;
+    b.exec = ex;
+    b.graph_key = key;
+    return MH_OK;
+}
+
+bool block_overlap(const uint32_t *X, int64_t NX, int64_t rx, int64_t cx, int64_t xr, int64_t xc,
+                   const uint32_t *Y, int64_t NY, int64_t ry, int64_t cy, int64_t yr, int64_t yc)
+{
+    Product a{}, b{};
+    a.C = const_cast<uint32_t *>(X);
+    a.NC = NX;
+    a.rc = rx;
+    a.cc = cx;
+    a.m = xr;
+    a.n = xc;
+    b.C = const_cast<uint32_t *>(Y);
+    b.NC = NY;
+    b.rc = ry;
+    b.cc = cy;
+    b.m = yr;
+    b.n = yc;
+    return outputs_alias(a, b);
+}
+
+}  // namespace
+
+hipError_t launch_reset_counters(uint64_t *counters, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters);
+    return hipGetLastError();
+}
+
+void batched_release(mh_ctx *ctx)
+{
+    BatchedState &b = ctx->batched;
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    if (b.capture_stream) (void)hipStreamDestroy(b.capture_stream);
+    if (b.queue_dev) (void)hipFree(b.queue_dev);
+    if (b.queue_host) (void)hipHostFree(b.queue_host);
+    if (b.counters) (void)hipFree(b.counters);
+    if (b.staging_free) (void)hipEventDestroy(b.staging_free);
+    b = BatchedState();
+}
 
 }  // namespace mh
 
@@ -14,12 +174,159 @@ extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, in
                                             uint32_t p, int32_t T, int32_t mode,
                                             hipStream_t stream)
 {
-    if (!ctx || (count > 0 && !d) || count < 0) return MH_E_INVALID;
+    if (!ctx || count < 0 || (count > 0 && !d)) return MH_E_INVALID;
+    if (mode < MH_MODE_AUTO || mode > MH_MODE_LIMB_I8) return MH_E_UNSUPPORTED;
+    if (!valid_T(T)) return MH_E_UNSUPPORTED;
+    if (p < 2u || p > 0x7FFFFFFFu) return MH_E_MODULUS;
+    // Validate every product first: a failing call has no effect.
+    std::vector<Product> prods(count);
     for (int32_t i = 0; i < count; ++i) {
-        mh_status s = mh_matmul_modp(ctx, d[i].C, d[i].NC, d[i].rc, d[i].cc, d[i].A, d[i].NA,
-                                     d[i].ra, d[i].ca, d[i].B, d[i].NB, d[i].rb, d[i].cb, d[i].m,
-                                     d[i].k, d[i].n, p, T, mode, stream);
+        Product &pr = prods[i];
+        pr = Product{};
+        pr.C = d[i].C;
+        pr.A = d[i].A;
+        pr.B = d[i].B;
+        pr.NC = d[i].NC;
+        pr.NA = d[i].NA;
+        pr.NB = d[i].NB;
+        pr.rc = d[i].rc;
+        pr.cc = d[i].cc;
+        pr.ra = d[i].ra;
+        pr.ca = d[i].ca;
+        pr.rb = d[i].rb;
+        pr.cb = d[i].cb;
+        pr.m = d[i].m;
+        pr.k = d[i].k;
+        pr.n = d[i].n;
+        pr.p = p;
+        pr.T = T;
+        pr.logT = log2i(T);
+        mh_status s = validate_product(pr, true);
         if (s != MH_OK) return s;
     }
-    return MH_OK;
+    // No output block may overlap another output block or any input block.
+    for (int32_t i = 0; i < count; ++i) {
+        const Product &x = prods[i];
+        if (x.m == 0 || x.n == 0) continue;
+        for (int32_t j = 0; j < count; ++j) {
+            const Product &y = prods[j];
+            if (j != i && y.m > 0 && y.n > 0 &&
+                block_overlap(x.C, x.NC, x.rc, x.cc, x.m, x.n, y.C, y.NC, y.rc, y.cc, y.m, y.n))
+                return MH_E_ALIAS;
+            if (block_overlap(x.C, x.NC, x.rc, x.cc, x.m, x.n, y.A, y.NA, y.ra, y.ca, y.m, y.k) ||
+                block_overlap(x.C, x.NC, x.rc, x.cc, x.m, x.n, y.B, y.NB, y.rb, y.cb, y.k, y.n))
+                return MH_E_ALIAS;
+        }
+    }
+    DeviceGuard g(ctx->device);
+    std::vector<int32_t> live;
+    for (int32_t i = 0; i < count; ++i)
+        if (prods[i].m > 0 && prods[i].n > 0 && prods[i].k > 0) live.push_back(i);
+    if (live.empty()) return MH_OK;
+
+    if (mode == MH_MODE_PLAIN_U32) {
+        // The plain form has no batched kernel: products run one after another.
+        for (int32_t i : live) {
+            Plan pl;
+            plan_product(prods[i], MH_MODE_PLAIN_U32, pl);
+            mh_status s = run_plain(ctx, pl, stream);
+            if (s != MH_OK) return s;
+        }
+        return MH_OK;
+    }
+
+    const int L = limbs_for(p);
+    std::vector<Plan> plans(live.size());
+    for (size_t q = 0; q < live.size(); ++q) plan_product(prods[live[q]], MH_MODE_LIMB_I8, plans[q]);
+    const int cfg = batch_cfg(L, plans);
+    for (size_t q = 0; q < live.size(); ++q)
+        plan_product(prods[live[q]], MH_MODE_LIMB_I8, plans[q], cfg);
+    // Longest-processing-time order: every output block of a product costs
+    // its k, so products with the longest k go first.
+    std::vector<size_t> order(plans.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return plans[a].kpad > plans[b].kpad; });
+
+    // Panels of every product in the context workspace.
+    std::vector<size_t> aoff(plans.size()), boff(plans.size());
+    size_t total = 0;
+    for (size_t q = 0; q < plans.size(); ++q) {
+        const Plan &pl = plans[q];
+        const size_t nkb = size_t(pl.kpad / 32);
+        aoff[q] = total;
+        total += align256(size_t(pl.prow) * nkb * 32 * L);
+        boff[q] = total;
+        total += align256(size_t(pl.pcol) * nkb * 32 * L);
+    }
+    const int64_t ncalls = int64_t(plans.size());
+    mh_status s = ensure_queue(ctx, ncalls);
+    if (s != MH_OK) return s;
+    char *ws = (char *)workspace(ctx, total + 256);
+    if (!ws) return MH_E_NOMEM;
+    BatchedState &b = ctx->batched;
+
+    // The staging buffer may still be read by the previous batch's copy.
+    if (hipEventSynchronize(b.staging_free) != hipSuccess) return note_error(ctx, hipErrorUnknown);
+    const QueueView hq = queue_view(b.queue_host, b.queue_cap);
+    int64_t pack_total = 0, tile_total = 0;
+    for (int64_t q = 0; q < ncalls; ++q) {
+        const Plan &pl = plans[order[q]];
+        const Product &pr = pl.pr;
+        const int64_t nkb = pl.kpad / 32;
+        int8_t *Ap = (int8_t *)(ws + aoff[order[q]]);
+        int8_t *Bp = (int8_t *)(ws + boff[order[q]]);
+        PackTask &ta = hq.packs[2 * q];
+        PackTask &tb = hq.packs[2 * q + 1];
+        ta = PackTask{pr.A, Ap, pr.ra, pr.ca, pl.sr, pr.m, pr.k, pl.prow, nkb, 0, pr.logT};
+        tb = PackTask{pr.B, Bp, pr.rb, pr.cb, pl.sc, pr.n, pr.k, pl.pcol, nkb, 1, pr.logT};
+        hq.pack_prefix[2 * q] = pack_total;
+        pack_total += (pl.prow / 64) * ((nkb + 1) / 2);
+        hq.pack_prefix[2 * q + 1] = pack_total;
+        pack_total += (pl.pcol / 64) * ((nkb + 1) / 2);
+        LimbArgs &a = hq.calls[q];
+        std::memset(&a, 0, sizeof(a));
+        a.Ap = Ap;
+        a.Bp = Bp;
+        a.nkb = nkb;
+        a.kb_per_red = pl.kblock / 32;
+        a.C = pr.C;
+        a.row0C = pl.row0C;
+        a.col0C = pl.col0C;
+        a.sr = pl.sr;
+        a.sc = pl.sc;
+        a.m = pr.m;
+        a.n = pr.n;
+        a.grid_m = pl.grid_m;
+        a.grid_n = pl.grid_n;
+        a.p = p;
+        a.mu = ~uint64_t(0) / p;
+        a.bias = ((uint64_t(1) << 31) + p - 1) / p * p;
+        a.pinv = 1.0 / double(p);
+        a.logT = pr.logT;
+        hq.tile_prefix[q] = tile_total;
+        tile_total += pl.grid_m * pl.grid_n;
+    }
+    hq.pack_prefix[2 * ncalls] = pack_total;
+    hq.tile_prefix[ncalls] = tile_total;
+    BatchHeader &h = *hq.hdr;
+    std::memset(&h, 0, sizeof(h));
+    h.npack = 2 * ncalls;
+    h.ncalls = ncalls;
+    h.pack_chunks = pack_total;
+    h.gemm_tiles = tile_total;
+    h.p = p;
+    h.L = L;
+
+    s = ensure_graph(ctx, cfg, L);
+    if (s != MH_OK) return s;
+    hipError_t e = hipMemcpyAsync(b.queue_dev, b.queue_host, queue_bytes(b.queue_cap),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(b.staging_free, stream);
+    if (e != hipSuccess) return note_error(ctx, e);
+    TimedLaunch t;
+    record_start(ctx, MH_K_BATCHED, stream, t);
+    e = hipGraphLaunch(b.exec, stream);
+    record_end(ctx, stream, t);
+    return note_error(ctx, e);
 }

@@ -18,16 +18,15 @@ struct TimedLaunch {
 
 // State of the batched path (persistent kernels, queue, graph).
 struct BatchedState {
-    void *queue_dev = nullptr;       // device copy of the task queue
-    size_t queue_cap = 0;
-    void *queue_host = nullptr;      // pinned staging buffer
-    size_t queue_host_cap = 0;
-    hipEvent_t staging_free = nullptr;  // recorded after the H2D copy of the last call
-    int *counters = nullptr;         // device work counters
+    void *queue_dev = nullptr;          // device copy of the task queue
+    void *queue_host = nullptr;         // pinned staging buffer of the same layout
+    int64_t queue_cap = 0;              // products the queue buffers hold
+    hipEvent_t staging_free = nullptr;  // recorded after the last host-to-device queue copy
+    uint64_t *counters = nullptr;       // device work counters (pack, GEMM)
+    hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int graph_key = -1;              // kernel configuration the graph was captured for
-    void *graph_queue = nullptr;     // queue address baked into the graph
+    int graph_key = -1;                 // kernel configuration the graph was captured for
 };
 
 struct DeviceGuard {
@@ -42,6 +41,8 @@ void record_end(mh_ctx *ctx, hipStream_t s, TimedLaunch &t);
 void *workspace(mh_ctx *ctx, size_t bytes);
 bool outputs_alias(const Product &x, const Product &y);
 void batched_release(mh_ctx *ctx);
+mh_status run_plain(mh_ctx *ctx, const Plan &pl, hipStream_t s);
+mh_status run_limb(mh_ctx *ctx, const Plan &pl, hipStream_t s);
 
 }  // namespace mh
 

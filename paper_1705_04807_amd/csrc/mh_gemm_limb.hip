@@ -28,15 +28,14 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-template <int L, int WM, int WN, int WAVES_M, int WAVES_N>
-__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb(LimbArgs a)
+// One workgroup's output block (gm, gn) of the product described by `a`.
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS>
+__device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t gn)
 {
     constexpr int S = 2 * L - 1;
     constexpr int BM = 32 * WM * WAVES_M, BN = 32 * WN * WAVES_N;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wmi = wave / WAVES_N, wni = wave % WAVES_N;
-    int64_t gm, gn;
-    tile_of(blockIdx.x, a.grid_m, a.grid_n, 8, gm, gn);
 
     const int64_t slabA = gm * (WM * WAVES_M) + wmi * WM;
     const int64_t slabB = gn * (WN * WAVES_N) + wni * WN;
@@ -58,20 +57,40 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb(LimbArgs a
     // Output (row, col) of a 32x32 block sits in lane col + 32 * ((row / 4) & 1),
     // register 4 * (row / 8) + row % 4.
     auto flush = [&]() {
-        uint32_t r[WM][WN][16];
+        // Horner in fp64, two shifts per reduction: with r < p < 2^31 and
+        // |T_s| < 2^31, x = 65536 r + 256 T_s + T_{s-1} has |x| < 2^48, so x and
+        // x - q p are exact doubles; q = floor(x / p) from the rounded
+        // reciprocal is off by at most one (|x / p| error < 2^-4), which the two
+        // corrections absorb.  Result: r = sum_s 256^s T_s mod p in [0, p).
+        const double pd = double(a.p), pinv = a.pinv;
+        auto red = [&](double x) {
+            const double q = floor(x * pinv);
+            double r = fma(-q, pd, x);
+            r = r < 0.0 ? r + pd : r;
+            r = r >= pd ? r - pd : r;
+            return r;
+        };
+        double r[WM][WN][16];
         static_for<WM>([&](auto i) {
-            static_for<WN>([&](auto j) { static_for<16>([&](auto v) { r[i][j][v] = 0; }); });
+            static_for<WN>([&](auto j) {
+                static_for<16>([&](auto v) {
+                    r[i][j][v] = red(double(acc[S - 1][i][j][int(v)]));
+                });
+                acc[S - 1][i][j] = v16i{0};
+            });
         });
-        static_for<S>([&](auto q) {
-            constexpr int s = S - 1 - q;
+        static_for<(S - 1) / 2>([&](auto q) {
+            constexpr int hi = S - 2 - 2 * q, lo = hi - 1;
             static_for<WM>([&](auto i) {
                 static_for<WN>([&](auto j) {
                     static_for<16>([&](auto v) {
-                        const uint64_t x =
-                            (uint64_t(r[i][j][v]) << 8) + a.bias + int64_t(acc[s][i][j][int(v)]);
-                        r[i][j][v] = mod_u64(x, a.p, a.mu);
+                        const double x = fma(r[i][j][v], 65536.0,
+                                             fma(double(acc[hi][i][j][int(v)]), 256.0,
+                                                 double(acc[lo][i][j][int(v)])));
+                        r[i][j][v] = red(x);
                     });
-                    acc[s][i][j] = v16i{0};
+                    acc[hi][i][j] = v16i{0};
+                    acc[lo][i][j] = v16i{0};
                 });
             });
         });
@@ -85,7 +104,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb(LimbArgs a
                     const int64_t rho = gm * BM + (wmi * WM + i) * 32 + row;
                     if (rho < a.sr || rho >= a.sr + a.m) return;
                     const uint64_t off = mh_offset(uint64_t(a.row0C + rho), ccol, a.logT);
-                    uint32_t c = a.C[off] + r[i][j][v];
+                    uint32_t c = a.C[off] + uint32_t(r[i][j][v]);
                     if (c >= a.p) c -= a.p;
                     a.C[off] = c;
                 });
@@ -93,62 +112,280 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb(LimbArgs a
         });
     };
 
-    for (int64_t kb0 = 0; kb0 < nkb; kb0 += a.kb_per_red) {
-        const int64_t kb1 = (kb0 + a.kb_per_red < nkb) ? kb0 + a.kb_per_red : nkb;
-        for (int64_t kb = kb0; kb < kb1; ++kb) {
-            v4i fa[WM][L], fb[WN][L];
+    // Fragments of k-blocks kb .. kb+KS-1: WM A slabs and WN B slabs, L digit
+    // planes each.
+    using FragA = v4i[KS][WM][L];
+    using FragB = v4i[KS][WN][L];
+    auto load = [&](FragA &fa, FragB &fb, int64_t kb) {
+        static_for<KS>([&](auto q) {
             static_for<WM>([&](auto i) {
-                static_for<L>([&](auto t) { fa[i][t] = pa[i * slab_stride + (kb * L + t) * 64]; });
+                static_for<L>([&](auto t) {
+                    fa[q][i][t] = pa[i * slab_stride + ((kb + q) * L + t) * 64];
+                });
             });
             static_for<WN>([&](auto j) {
-                static_for<L>([&](auto u) { fb[j][u] = pb[j * slab_stride + (kb * L + u) * 64]; });
+                static_for<L>([&](auto u) {
+                    fb[q][j][u] = pb[j * slab_stride + ((kb + q) * L + u) * 64];
+                });
             });
+        });
+    };
+    auto mma = [&](const FragA &fa, const FragB &fb) {
+        static_for<KS>([&](auto q) {
             static_for<L>([&](auto t) {
                 static_for<L>([&](auto u) {
                     static_for<WM>([&](auto i) {
                         static_for<WN>([&](auto j) {
                             acc[t + u][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                fa[i][t], fb[j][u], acc[t + u][i][j], 0, 0, 0);
+                                fa[q][i][t], fb[q][j][u], acc[t + u][i][j], 0, 0, 0);
                         });
                     });
                 });
             });
+        });
+    };
+
+    if constexpr (!LDS) {
+        // Two register sets: the loads of the next stage (KS k-blocks) are in
+        // flight while the MFMAs of the current one run.  nkb and kb_per_red
+        // are multiples of KS.
+        FragA fa0, fa1;
+        FragB fb0, fb1;
+        for (int64_t kb0 = 0; kb0 < nkb; kb0 += a.kb_per_red) {
+            const int64_t kb1 = (kb0 + a.kb_per_red < nkb) ? kb0 + a.kb_per_red : nkb;
+            load(fa0, fb0, kb0);
+            int64_t kb = kb0;
+            for (; kb + 2 * KS <= kb1; kb += 2 * KS) {
+                load(fa1, fb1, kb + KS);
+                mma(fa0, fb0);
+                if (kb + 2 * KS < kb1) load(fa0, fb0, kb + 2 * KS);
+                mma(fa1, fb1);
+            }
+            if (kb < kb1) mma(fa0, fb0);
+            flush();
         }
-        flush();
+    } else {
+        // The workgroup's blocks of one stage (all A slabs, then all B slabs,
+        // KS k-blocks x L limbs each) go global -> LDS with one 16-byte
+        // global_load_lds per lane and block, spread over the waves; LDS is
+        // double-buffered by stage.  Blocks land in lane order, so each wave
+        // reads its fragments back with conflict-free 16-byte LDS reads, and
+        // every A or B block crosses the L2 once per workgroup instead of
+        // once per wave that uses it.
+        extern __shared__ v4i lds_buf[];  // [2][NBLK][64]
+        constexpr int NW = WAVES_M * WAVES_N;
+        constexpr int NA = WM * WAVES_M * KS * L;
+        constexpr int NBLK = (WM * WAVES_M + WN * WAVES_N) * KS * L;
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
+        const int64_t slabA0 = gm * (WM * WAVES_M), slabB0 = gn * (WN * WAVES_N);
+        const v4i *ga = reinterpret_cast<const v4i *>(a.Ap) + lane;
+        const v4i *gb = reinterpret_cast<const v4i *>(a.Bp) + lane;
+        auto issue = [&](int64_t st, int buf) {
+            const int64_t kb = st * KS;
+            static_for<(NBLK + NW - 1) / NW>([&](auto r) {
+                const int b = wv + NW * r;
+                if (b < NBLK) {
+                    const v4i *src;
+                    if (b < NA) {
+                        const int sl = b / (KS * L), q = (b / L) % KS, t = b % L;
+                        src = ga + (((slabA0 + sl) * nkb + kb + q) * L + t) * 64;
+                    } else {
+                        const int bb = b - NA;
+                        const int sl = bb / (KS * L), q = (bb / L) % KS, t = bb % L;
+                        src = gb + (((slabB0 + sl) * nkb + kb + q) * L + t) * 64;
+                    }
+                    __builtin_amdgcn_global_load_lds(
+                        src, (__attribute__((address_space(3))) void *)(lds_buf + (buf * NBLK + b) * 64),
+                        16, 0, 0);
+                }
+            });
+        };
+        const int64_t nst = nkb / KS, st_red = a.kb_per_red / KS;
+        issue(0, 0);
+        for (int64_t st = 0; st < nst; ++st) {
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's blocks of stage st landed
+            __syncthreads();                     // every wave's did; buffer (st+1)&1 is free again
+            if (st + 1 < nst) issue(st + 1, int((st + 1) & 1));
+            const v4i *sb = lds_buf + (st & 1) * (NBLK * 64) + lane;
+            static_for<KS>([&](auto q) {
+                v4i fa[WM][L], fb[WN][L];
+                static_for<WM>([&](auto i) {
+                    static_for<L>([&](auto t) {
+                        fa[i][t] = sb[(((wmi * WM + i) * KS + q) * L + t) * 64];
+                    });
+                });
+                static_for<WN>([&](auto j) {
+                    static_for<L>([&](auto u) {
+                        fb[j][u] = sb[(NA + ((wni * WN + j) * KS + q) * L + u) * 64];
+                    });
+                });
+                static_for<L>([&](auto t) {
+                    static_for<L>([&](auto u) {
+                        static_for<WM>([&](auto i) {
+                            static_for<WN>([&](auto j) {
+                                acc[t + u][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                    fa[i][t], fb[j][u], acc[t + u][i][j], 0, 0, 0);
+                            });
+                        });
+                    });
+                });
+            });
+            if ((st + 1) % st_red == 0 || st + 1 == nst) flush();
+        }
     }
 }
 
-template <int L, int WM, int WN, int WAVES_M, int WAVES_N>
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb(LimbArgs a)
+{
+    int64_t gm, gn;
+    tile_of(blockIdx.x, a.grid_m, a.grid_n, 8, gm, gn);
+    gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS>(a, gm, gn);
+}
+
+// Persistent form for a batch of products: every workgroup pops output
+// blocks from the queue through an atomic counter until none is left (the
+// exit test is the same for all waves of the group).  Blocks are numbered
+// call by call in the queue's order (largest k first); a binary search over
+// the per-call prefix sums finds the call of a block.
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb_batched(QueueView q,
+                                                                              uint64_t *counter)
+{
+    __shared__ int64_t task_s;
+    const int64_t total = q.hdr->gemm_tiles;
+    const int64_t ncalls = q.hdr->ncalls;
+    for (;;) {
+        if (threadIdx.x == 0) task_s = int64_t(atomicAdd((unsigned long long *)counter, 1ull));
+        __syncthreads();
+        const int64_t t = task_s;
+        __syncthreads();
+        if (t >= total) break;
+        int64_t lo = 0, hi = ncalls;  // tile_prefix[lo] <= t < tile_prefix[hi]
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (q.tile_prefix[mid] <= t) lo = mid; else hi = mid;
+        }
+        const LimbArgs a = q.calls[lo];
+        const int64_t local = t - q.tile_prefix[lo];
+        gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS>(a, local / a.grid_n, local % a.grid_n);
+    }
+}
+
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS>
+constexpr size_t lds_bytes()
+{
+    return LDS ? size_t(2) * (WM * WAVES_M + WN * WAVES_N) * KS * L * 1024 : 0;
+}
+
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS>
 hipError_t launch_one(const LimbArgs &a, hipStream_t s)
 {
     const int64_t groups = a.grid_m * a.grid_n;
     if (groups <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_gemm_limb<L, WM, WN, WAVES_M, WAVES_N>), dim3(unsigned(groups)),
-                       dim3(64 * WAVES_M * WAVES_N), 0, s, a);
+    if (a.nkb % KS || a.kb_per_red % KS) return hipErrorInvalidValue;
+    auto kern = k_gemm_limb<L, WM, WN, WAVES_M, WAVES_N, KS, LDS>;
+    const size_t shm = lds_bytes<L, WM, WN, WAVES_M, WAVES_N, KS, LDS>();
+    if (shm > 65536) {
+        static bool set = false;
+        if (!set && hipFuncSetAttribute((const void *)kern,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        int(shm)) != hipSuccess)
+            return hipErrorInvalidValue;
+        set = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(unsigned(groups)), dim3(64 * WAVES_M * WAVES_N), shm, s, a);
     return hipGetLastError();
 }
 
-// Configuration table.  (2L-1) * WM * WN accumulator tiles of 16 registers
-// must fit beside the fragments: at most 14 tiles.
+// Configuration table: {id, WM, WN, waves_m, waves_n, KS, LDS}.  (2L-1) * WM * WN
+// accumulator tiles of 16 registers must fit beside the fragments: at most
+// 14 tiles.
 const LimbKernelCfg kCfgs[] = {
-    {0, 1, 2, 2, 2},  // 64 x 128
-    {1, 1, 1, 2, 2},  // 64 x 64
-    {2, 2, 1, 2, 2},  // 128 x 64
-    {3, 2, 2, 2, 2},  // 128 x 128 (L <= 2)
+    {0, 1, 2, 2, 2, 1, 0},  // 64 x 128
+    {1, 1, 1, 2, 2, 1, 0},  // 64 x 64
+    {2, 2, 1, 2, 2, 1, 0},  // 128 x 64
+    {3, 2, 2, 2, 2, 1, 0},  // 128 x 128 (L <= 2)
+    {4, 1, 2, 2, 2, 2, 0},  // 64 x 128, 64-deep stages
+    {5, 2, 2, 2, 2, 2, 0},  // 128 x 128, 64-deep stages (L <= 2)
+    {6, 1, 1, 2, 2, 2, 0},  // 64 x 64, 64-deep stages
+    {7, 1, 2, 2, 2, 2, 1},   // 64 x 128, LDS-shared stages
+    {8, 2, 2, 2, 2, 2, 1},   // 128 x 128, LDS-shared stages (L <= 2)
+    {9, 1, 1, 2, 2, 2, 1},   // 64 x 64, LDS-shared stages
+    {10, 2, 1, 2, 2, 2, 1},  // 128 x 64, LDS-shared stages
 };
 
 bool cfg_fits(int L, const LimbKernelCfg &c) { return (2 * L - 1) * c.wm * c.wn <= 14; }
+
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS>
+hipError_t launch_batched_one(const QueueView &q, uint64_t *counter, int num_cu, hipStream_t s)
+{
+    auto kern = k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS>;
+    const size_t shm = lds_bytes<L, WM, WN, WAVES_M, WAVES_N, KS, LDS>();
+    if (shm > 65536) {
+        static bool set = false;
+        if (!set && hipFuncSetAttribute((const void *)kern,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        int(shm)) != hipSuccess)
+            return hipErrorInvalidValue;
+        set = true;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * WAVES_M * WAVES_N, shm) !=
+            hipSuccess || per_cu < 1)
+        per_cu = 1;
+    hipLaunchKernelGGL(kern, dim3(unsigned(num_cu * per_cu)), dim3(64 * WAVES_M * WAVES_N), shm,
+                       s, q, counter);
+    return hipGetLastError();
+}
+
+template <int L>
+hipError_t dispatch_batched_L(int cfg, const QueueView &q, uint64_t *counter, int num_cu,
+                              hipStream_t s)
+{
+    switch (cfg) {
+    case 0: return launch_batched_one<L, 1, 2, 2, 2, 1, false>(q, counter, num_cu, s);
+    case 1: return launch_batched_one<L, 1, 1, 2, 2, 1, false>(q, counter, num_cu, s);
+    case 2: return launch_batched_one<L, 2, 1, 2, 2, 1, false>(q, counter, num_cu, s);
+    case 3:
+        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 1, false>(q, counter, num_cu, s);
+        return hipErrorInvalidValue;
+    case 4: return launch_batched_one<L, 1, 2, 2, 2, 2, false>(q, counter, num_cu, s);
+    case 5:
+        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 2, false>(q, counter, num_cu, s);
+        return hipErrorInvalidValue;
+    case 6: return launch_batched_one<L, 1, 1, 2, 2, 2, false>(q, counter, num_cu, s);
+    case 7: return launch_batched_one<L, 1, 2, 2, 2, 2, true>(q, counter, num_cu, s);
+    case 8:
+        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 2, true>(q, counter, num_cu, s);
+        return hipErrorInvalidValue;
+    case 9: return launch_batched_one<L, 1, 1, 2, 2, 2, true>(q, counter, num_cu, s);
+    case 10: return launch_batched_one<L, 2, 1, 2, 2, 2, true>(q, counter, num_cu, s);
+    }
+    return hipErrorInvalidValue;
+}
 
 template <int L>
 hipError_t dispatch_L(int cfg, const LimbArgs &a, hipStream_t s)
 {
     switch (cfg) {
-    case 0: return launch_one<L, 1, 2, 2, 2>(a, s);
-    case 1: return launch_one<L, 1, 1, 2, 2>(a, s);
-    case 2: return launch_one<L, 2, 1, 2, 2>(a, s);
+    case 0: return launch_one<L, 1, 2, 2, 2, 1, false>(a, s);
+    case 1: return launch_one<L, 1, 1, 2, 2, 1, false>(a, s);
+    case 2: return launch_one<L, 2, 1, 2, 2, 1, false>(a, s);
     case 3:
-        if constexpr (L <= 2) return launch_one<L, 2, 2, 2, 2>(a, s);
+        if constexpr (L <= 2) return launch_one<L, 2, 2, 2, 2, 1, false>(a, s);
         return hipErrorInvalidValue;
+    case 4: return launch_one<L, 1, 2, 2, 2, 2, false>(a, s);
+    case 5:
+        if constexpr (L <= 2) return launch_one<L, 2, 2, 2, 2, 2, false>(a, s);
+        return hipErrorInvalidValue;
+    case 6: return launch_one<L, 1, 1, 2, 2, 2, false>(a, s);
+    case 7: return launch_one<L, 1, 2, 2, 2, 2, true>(a, s);
+    case 8:
+        if constexpr (L <= 2) return launch_one<L, 2, 2, 2, 2, 2, true>(a, s);
+        return hipErrorInvalidValue;
+    case 9: return launch_one<L, 1, 1, 2, 2, 2, true>(a, s);
+    case 10: return launch_one<L, 2, 1, 2, 2, 2, true>(a, s);
     }
     return hipErrorInvalidValue;
 }
@@ -161,9 +398,22 @@ const LimbKernelCfg &limb_cfg(int idx) { return kCfgs[idx]; }
 int limb_cfg_default(int L, int64_t m, int64_t n, int64_t k)
 {
     (void)k;
-    if (m * n <= int64_t(512) * 512) return 1;
-    if (L <= 2) return 3;
-    return 0;
+    if (m * n <= int64_t(512) * 512) return 6;  // 64 x 64 output blocks
+    if (L <= 2) return 5;                      // 128 x 128
+    return 4;                                  // 64 x 128
+}
+
+hipError_t launch_gemm_limb_batched(int cfg, int L, const QueueView &q, uint64_t *counter,
+                                    int num_cu, hipStream_t s)
+{
+    if (cfg < 0 || cfg >= limb_cfg_count() || !cfg_fits(L, kCfgs[cfg])) return hipErrorInvalidValue;
+    switch (L) {
+    case 1: return dispatch_batched_L<1>(cfg, q, counter, num_cu, s);
+    case 2: return dispatch_batched_L<2>(cfg, q, counter, num_cu, s);
+    case 3: return dispatch_batched_L<3>(cfg, q, counter, num_cu, s);
+    case 4: return dispatch_batched_L<4>(cfg, q, counter, num_cu, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_gemm_limb(int cfg, int L, const LimbArgs &a, hipStream_t s)

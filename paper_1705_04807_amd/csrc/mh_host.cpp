@@ -348,7 +348,7 @@ void segments(int64_t len, int64_t offA, int64_t offB, int32_t T, std::vector<in
     cuts.push_back(len);
 }
 
-void plan_product(const Product &p, int mode, Plan &pl)
+void plan_product(const Product &p, int mode, Plan &pl, int forced_cfg)
 {
     pl.pr = p;
     const int64_t T = p.T;
@@ -361,6 +361,12 @@ void plan_product(const Product &p, int mode, Plan &pl)
     pl.kblock = kblock_for(pl.L);
     if (mode == MH_MODE_LIMB_I8) {
         pl.limb_cfg = limb_cfg_default(pl.L, p.m, p.n, p.k);
+        if (const char *e = std::getenv("MH_LIMB_CFG")) {  // explicit override (tuning runs)
+            int c = std::atoi(e);
+            if (c >= 0 && c < limb_cfg_count() && (2 * pl.L - 1) * limb_cfg(c).wm * limb_cfg(c).wn <= 14)
+                pl.limb_cfg = c;
+        }
+        if (forced_cfg >= 0) pl.limb_cfg = forced_cfg;
         const LimbKernelCfg &c = limb_cfg(pl.limb_cfg);
         pl.tile_m = c.tile_m();
         pl.tile_n = c.tile_n();
@@ -379,7 +385,7 @@ void plan_product(const Product &p, int mode, Plan &pl)
     pl.grid_n = pl.pcol / pl.tile_n;
     if (mode == MH_MODE_LIMB_I8) {
         pl.sk = 0;
-        pl.kpad = (p.k + 31) / 32 * 32;
+        pl.kpad = (p.k + 63) / 64 * 64;  // an even number of 32-deep k-blocks
         pl.in_place = false;
     } else {
         // In place when A's tile rows line up with the panel rows, B's tile
@@ -455,6 +461,7 @@ extern "C" mh_status mh_plan_describe(int64_t NC, int64_t rc, int64_t cc, int64_
     out->tile_n = pl.tile_n;
     out->limbs = pl.mode == MH_MODE_LIMB_I8 ? pl.L : 0;
     out->kblock = pl.mode == MH_MODE_LIMB_I8 ? pl.kblock : 0;
+    out->kernel_cfg = pl.mode == MH_MODE_LIMB_I8 ? pl.limb_cfg : -1;
     out->gemm_tasks = (m > 0 && n > 0) ? pl.grid_m * pl.grid_n : 0;
     if (pl.mode == MH_MODE_LIMB_I8 && m > 0 && n > 0 && k > 0) {
         int64_t nkb = pl.kpad / 32;
@@ -579,7 +586,7 @@ extern "C" mh_status mh_layout_to_cartesian(mh_ctx *ctx, uint32_t *dst, int64_t 
 
 namespace mh {
 
-static uint64_t barrett_mu(uint32_t p) { return ~uint64_t(0) / p; }
+uint64_t barrett_mu(uint32_t p) { return ~uint64_t(0) / p; }
 
 static uint64_t horner_bias(uint32_t p)
 {
@@ -687,6 +694,7 @@ mh_status run_limb(mh_ctx *ctx, const Plan &pl, hipStream_t s)
     a.p = p.p;
     a.mu = barrett_mu(p.p);
     a.bias = horner_bias(p.p);
+    a.pinv = 1.0 / double(p.p);
     a.logT = p.logT;
     record_start(ctx, MH_K_GEMM_LIMB, s, t);
     e = launch_gemm_limb(pl.limb_cfg, L, a, s);

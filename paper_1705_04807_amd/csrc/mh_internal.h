@@ -93,20 +93,20 @@ inline int limbs_for(uint32_t p)
     return 4;
 }
 
-inline int64_t limb_threshold(int L)
+__host__ __device__ inline int64_t limb_threshold(int L)
 {
     int64_t h = 0, w = 1;
     for (int t = 0; t < L; ++t) { h += 127 * w; w *= 256; }
     return h;
 }
 
-// Longest k-block (multiple of the MFMA depth 32) whose shift accumulators
+// Longest k-block (multiple of 64, two MFMA depths) whose shift accumulators
 // T_s = sum_{t+u=s} A_t B_u cannot leave int32: |d_t d_u| <= 2^14 and at most
 // L digit pairs meet in one shift, so |T_s| <= kappa * L * 2^14 < 2^31.
 inline int kblock_for(int L)
 {
     int64_t kap = ((int64_t(1) << 31) - 1) / (int64_t(L) << 14);
-    return int(kap / 32 * 32);
+    return int(kap / 64 * 64);
 }
 
 // ------------------------------------------------------------- geometry
@@ -132,6 +132,8 @@ struct LimbKernelCfg {
     int id;
     int wm, wn;          // 32x32 MFMA tiles per wave (rows, cols)
     int waves_m, waves_n;
+    int ks;              // 32-deep k-blocks per pipeline stage
+    int lds;             // 1: stages shared through LDS by the workgroup's waves
     int tile_m() const { return 32 * wm * waves_m; }
     int tile_n() const { return 32 * wn * waves_n; }
 };
@@ -169,7 +171,7 @@ bool valid_T(int32_t T);
 int log2i(int64_t x);
 mh_status check_parent(int64_t N, int32_t T);
 mh_status validate_product(const Product &p, bool need_ptrs);
-void plan_product(const Product &p, int mode, Plan &out);
+void plan_product(const Product &p, int mode, Plan &out, int forced_cfg = -1);
 void segments(int64_t len, int64_t offA, int64_t offB, int32_t T, std::vector<int64_t> &cuts);
 
 // limb kernel table
@@ -227,8 +229,70 @@ struct LimbArgs {
     uint32_t p;
     uint64_t mu;         // floor((2^64 - 1) / p)
     uint64_t bias;       // multiple of p, >= 2^31
+    double pinv;         // 1.0 / p rounded to nearest
     int logT;
 };
 hipError_t launch_gemm_limb(int cfg, int L, const LimbArgs &a, hipStream_t s);
+
+// ------------------------------------------------------------ batch queue
+//
+// Device-resident description of a batch of products, laid out in one
+// buffer with room for `cap` products: a header, one PackTask per operand
+// panel (A then B of each product), their chunk prefix sums, one LimbArgs
+// per product (in launch order: largest k first) and their output-block
+// prefix sums.
+
+struct PackTask {
+    const uint32_t *src;
+    int8_t *dst;
+    int64_t r0, c0, shift, R, K, prow, nkb;
+    int32_t trans, logT;
+};
+
+struct BatchHeader {
+    int64_t npack, ncalls, pack_chunks, gemm_tiles;
+    uint32_t p;
+    int32_t L;
+    int64_t pad[2];
+};
+
+struct QueueView {
+    BatchHeader *hdr;
+    PackTask *packs;        // [2 cap]
+    int64_t *pack_prefix;   // [2 cap + 1]
+    LimbArgs *calls;        // [cap]
+    int64_t *tile_prefix;   // [cap + 1]
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline size_t queue_bytes(int64_t cap)
+{
+    return align256(sizeof(BatchHeader)) + align256(sizeof(PackTask) * 2 * cap) +
+           align256(sizeof(int64_t) * (2 * cap + 1)) + align256(sizeof(LimbArgs) * cap) +
+           align256(sizeof(int64_t) * (cap + 1));
+}
+
+inline QueueView queue_view(void *base, int64_t cap)
+{
+    char *b = (char *)base;
+    QueueView q;
+    q.hdr = (BatchHeader *)b;
+    b += align256(sizeof(BatchHeader));
+    q.packs = (PackTask *)b;
+    b += align256(sizeof(PackTask) * 2 * cap);
+    q.pack_prefix = (int64_t *)b;
+    b += align256(sizeof(int64_t) * (2 * cap + 1));
+    q.calls = (LimbArgs *)b;
+    b += align256(sizeof(LimbArgs) * cap);
+    q.tile_prefix = (int64_t *)b;
+    return q;
+}
+
+hipError_t launch_pack_limb_batched(int L, const QueueView &q, uint64_t *counter, int num_cu,
+                                    hipStream_t s);
+hipError_t launch_gemm_limb_batched(int cfg, int L, const QueueView &q, uint64_t *counter,
+                                    int num_cu, hipStream_t s);
+hipError_t launch_reset_counters(uint64_t *counters, hipStream_t s);
 
 }  // namespace mh

@@ -90,15 +90,13 @@ __device__ __forceinline__ void digits16(const uint32_t *x, uint32_t p, int32_t 
 // shift, c0 + kap); trans = 1: src(r0 + kap, c0 + rho - shift).  Entries
 // with rho outside [shift, shift + R) or kap >= K are zero.
 template <int L, bool TRANS>
-__global__ __launch_bounds__(256) void k_pack_limb(int8_t *__restrict__ dst, int64_t nkb,
-                                                   const uint32_t *__restrict__ src, int64_t r0,
-                                                   int64_t c0, int64_t shift, int64_t R, int64_t K,
-                                                   int logT, uint32_t p, int32_t H)
+__device__ __forceinline__ void pack_chunk(int8_t *__restrict__ dst, int64_t nkb,
+                                           const uint32_t *__restrict__ src, int64_t r0,
+                                           int64_t c0, int64_t shift, int64_t R, int64_t K,
+                                           int logT, uint32_t p, int32_t H, int64_t rho0,
+                                           int64_t kap0, uint32_t *tile)
 {
-    __shared__ uint32_t tile[kChunk * kLdsStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t rho0 = int64_t(blockIdx.y) * kChunk;
-    const int64_t kap0 = int64_t(blockIdx.x) * kChunk;
 
     if (!TRANS) {
         // lanes walk the depth (source columns, contiguous inside a tile row)
@@ -152,6 +150,55 @@ __global__ __launch_bounds__(256) void k_pack_limb(int8_t *__restrict__ dst, int
     for (int t = 0; t < L; ++t) o[t * 64] = d[t];
 }
 
+template <int L, bool TRANS>
+__global__ __launch_bounds__(256) void k_pack_limb(int8_t *__restrict__ dst, int64_t nkb,
+                                                   const uint32_t *__restrict__ src, int64_t r0,
+                                                   int64_t c0, int64_t shift, int64_t R, int64_t K,
+                                                   int logT, uint32_t p, int32_t H)
+{
+    __shared__ uint32_t tile[kChunk * kLdsStride];
+    pack_chunk<L, TRANS>(dst, nkb, src, r0, c0, shift, R, K, logT, p, H,
+                         int64_t(blockIdx.y) * kChunk, int64_t(blockIdx.x) * kChunk, tile);
+}
+
+// Persistent form for a batch: workgroups pop 64 x 64 chunks of all the
+// operand panels of the batch through an atomic counter; a binary search
+// over the per-operand prefix sums finds the operand of a chunk.  The
+// barrier after reading the popped index also orders the LDS reuse between
+// consecutive chunks.
+template <int L>
+__global__ __launch_bounds__(256) void k_pack_limb_batched(QueueView q, uint64_t *counter)
+{
+    __shared__ uint32_t tile[kChunk * kLdsStride];
+    __shared__ int64_t chunk_s;
+    const int64_t total = q.hdr->pack_chunks;
+    const int64_t npack = q.hdr->npack;
+    const uint32_t p = q.hdr->p;
+    const int32_t H = int32_t(limb_threshold(L));
+    for (;;) {
+        if (threadIdx.x == 0) chunk_s = int64_t(atomicAdd((unsigned long long *)counter, 1ull));
+        __syncthreads();
+        const int64_t c = chunk_s;
+        __syncthreads();
+        if (c >= total) break;
+        int64_t lo = 0, hi = npack;  // pack_prefix[lo] <= c < pack_prefix[hi]
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (q.pack_prefix[mid] <= c) lo = mid; else hi = mid;
+        }
+        const PackTask t = q.packs[lo];
+        const int64_t local = c - q.pack_prefix[lo];
+        const int64_t kchunks = (t.nkb + 1) / 2;
+        const int64_t rho0 = (local / kchunks) * kChunk, kap0 = (local % kchunks) * kChunk;
+        if (t.trans)
+            pack_chunk<L, true>(t.dst, t.nkb, t.src, t.r0, t.c0, t.shift, t.R, t.K, t.logT, p, H,
+                                rho0, kap0, tile);
+        else
+            pack_chunk<L, false>(t.dst, t.nkb, t.src, t.r0, t.c0, t.shift, t.R, t.K, t.logT, p, H,
+                                 rho0, kap0, tile);
+    }
+}
+
 template <int L>
 hipError_t launch_limb_L(int8_t *dst, int64_t prow, int64_t nkb, const uint32_t *src, int64_t r0,
                          int64_t c0, int64_t shift, int64_t R, int64_t K, int trans, int logT,
@@ -179,6 +226,25 @@ hipError_t launch_pack_u32(uint32_t *dst, int64_t prow, int64_t pcol, const uint
     hipLaunchKernelGGL(k_pack_u32, dim3(unsigned(ntc), unsigned(ntr)), dim3(256), 0, s, dst, ntc,
                        src, srow0, scol0, vr0, vr1, vc0, vc1, logT);
     return hipGetLastError();
+}
+
+hipError_t launch_pack_limb_batched(int L, const QueueView &q, uint64_t *counter, int num_cu,
+                                    hipStream_t s)
+{
+    auto go = [&](auto kern) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        hipLaunchKernelGGL(kern, dim3(unsigned(num_cu * per_cu)), dim3(256), 0, s, q, counter);
+        return hipGetLastError();
+    };
+    switch (L) {
+    case 1: return go(k_pack_limb_batched<1>);
+    case 2: return go(k_pack_limb_batched<2>);
+    case 3: return go(k_pack_limb_batched<3>);
+    default: return go(k_pack_limb_batched<4>);
+    }
 }
 
 hipError_t launch_pack_limb(int8_t *dst, int64_t prow, int64_t nkb, const uint32_t *src,

@@ -121,3 +121,37 @@ def residues_torch(seed: int, p: int, rows: int, cols: int, ld: int | None = Non
 
 def residues_scalar(seed: int, p: int, i: int, j: int, ld: int) -> int:
     return splitmix64_scalar(seed, i * ld + j) % p
+
+
+def tu_level_batch(seed: int = 5000, count: int = 512, N: int = 8192, n_c_parents: int = 64,
+                   unit: int = 64, max_units: int = 32):
+    """Shapes and offsets of `count` independent products of one TU recursion level.
+
+    For each product and each of m, k, n independently: size = unit * u + r
+    with u uniform in 1..max_units and r uniform in 1..unit-1.  A and B
+    blocks lie anywhere in one shared N x N parent each (read-only overlap
+    allowed); product i writes C parent i mod n_c_parents, its C offset
+    redrawn until disjoint from the earlier blocks of that parent.  Draws
+    come from SplitMix64 seeded with `seed`, in a fixed order.
+    """
+    ctr = [0]
+
+    def draw(lo: int, hi: int) -> int:  # uniform integer in [lo, hi]
+        v = splitmix64_scalar(seed, ctr[0])
+        ctr[0] += 1
+        return lo + v % (hi - lo + 1)
+
+    used = [[] for _ in range(n_c_parents)]
+    calls = []
+    for i in range(count):
+        m, k, n = (unit * draw(1, max_units) + draw(1, unit - 1) for _ in range(3))
+        ci = i % n_c_parents
+        while True:
+            rc, cc = draw(0, N - m), draw(0, N - n)
+            if all(rc + m <= r or r + mm <= rc or cc + n <= c or c + nn <= cc
+                   for r, c, mm, nn in used[ci]):
+                break
+        used[ci].append((rc, cc, m, n))
+        calls.append(dict(ci=ci, rc=rc, cc=cc, m=m, k=k, n=n, ra=draw(0, N - m),
+                          ca=draw(0, N - k), rb=draw(0, N - k), cb=draw(0, N - n)))
+    return calls

@@ -1,0 +1,145 @@
+"""GPU parity of the batched persistent path (queue + graph replay) against the
+oracle.  Bar: bit-exact over every parent."""
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import (device_of, expected_view, host_of, parent_host, say,
+                            stream_handle, to_cart, to_mh, torch_cuda)
+
+pytestmark = pytest.mark.gpu
+
+P31 = 2**31 - 1
+
+
+@pytest.fixture(scope="module")
+def mh():
+    import paper_1705_04807_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mh):
+    torch_cuda()
+    c = mh.mh_ctx_create(0)
+    yield c
+    mh.mh_ctx_destroy(c)
+
+
+def draw_batch(g, count, NA, NB, NC, nC, smax):
+    """count products with disjoint C blocks spread over nC parents."""
+    calls, used = [], [[] for _ in range(nC)]
+    while len(calls) < count:
+        m, k, n = (int(g.integers(1, smax + 1)) for _ in range(3))
+        ci = len(calls) % nC
+        for _ in range(200):
+            rc, cc = int(g.integers(0, NC - m + 1)), int(g.integers(0, NC - n + 1))
+            if all(rc + m <= r or r + mm <= rc or cc + n <= c or c + nn <= cc
+                   for r, c, mm, nn in used[ci]):
+                break
+        else:
+            continue
+        used[ci].append((rc, cc, m, n))
+        calls.append(dict(ci=ci, rc=rc, cc=cc, m=m, k=k, n=n,
+                          ra=int(g.integers(0, NA - m + 1)), ca=int(g.integers(0, NA - k + 1)),
+                          rb=int(g.integers(0, NB - k + 1)), cb=int(g.integers(0, NB - n + 1))))
+    return calls
+
+
+def run_batch(mh, ctx, calls, A, B, Cs, Ad, Bd, Cds, NA, NB, NC, p, T, mode):
+    descs = mh.make_descs([dict(C=Cds[c["ci"]].data_ptr(), A=Ad.data_ptr(), B=Bd.data_ptr(),
+                                NC=NC, NA=NA, NB=NB, rc=c["rc"], cc=c["cc"], ra=c["ra"],
+                                ca=c["ca"], rb=c["rb"], cb=c["cb"], m=c["m"], k=c["k"],
+                                n=c["n"]) for c in calls])
+    mh.check(mh.mh_matmul_modp_batched(ctx, descs, len(calls), p, T, mode, stream_handle()),
+             "batched")
+    for c in calls:
+        Cs[c["ci"]] = expected_view(Cs[c["ci"]], A, B, p, c["rc"], c["cc"], c["ra"], c["ca"],
+                                    c["rb"], c["cb"], c["m"], c["k"], c["n"])
+    for ci, Cd in enumerate(Cds):
+        got = host_of(to_cart(mh, ctx, Cd, NC, T))
+        assert np.array_equal(got, Cs[ci]), "C parent %d differs" % ci
+    assert mh.mh_ctx_last_device_error(ctx) == 0
+
+
+@pytest.mark.parametrize("mode", [2, 1])
+@pytest.mark.parametrize("p,T", [(65521, 64), (P31, 32), (251, 16), ((1 << 24) - 3, 128)])
+def test_batched_random(mh, ctx, mode, p, T):
+    g = np.random.default_rng(900 + T + mode)
+    NA = NB = NC = 1024
+    nC = 3
+    A, B = parent_host(901, p, NA), parent_host(902, p, NB)
+    Cs = [parent_host(910 + i, p, NC) for i in range(nC)]
+    Ad, Bd = to_mh(mh, ctx, device_of(A), NA, T), to_mh(mh, ctx, device_of(B), NB, T)
+    Cds = [to_mh(mh, ctx, device_of(C), NC, T) for C in Cs]
+    calls = draw_batch(g, 24, NA, NB, NC, nC, 300)
+    say("batched", p, T, mode, len(calls))
+    run_batch(mh, ctx, calls, A, B, Cs, Ad, Bd, Cds, NA, NB, NC, p, T, mode)
+
+
+def test_batched_graph_replay_new_queue(mh, ctx):
+    # one captured graph, three batches with different contents and sizes
+    p, T = 65521, 64
+    NA = NB = NC = 1024
+    A, B = parent_host(921, p, NA), parent_host(922, p, NB)
+    Cs = [parent_host(930 + i, p, NC) for i in range(2)]
+    Ad, Bd = to_mh(mh, ctx, device_of(A), NA, T), to_mh(mh, ctx, device_of(B), NB, T)
+    Cds = [to_mh(mh, ctx, device_of(C), NC, T) for C in Cs]
+    g = np.random.default_rng(77)
+    for rep, (count, smax) in enumerate([(10, 400), (30, 150), (10, 400)]):
+        say("replay", rep)
+        calls = draw_batch(g, count, NA, NB, NC, 2, smax)
+        run_batch(mh, ctx, calls, A, B, Cs, Ad, Bd, Cds, NA, NB, NC, p, T, 2)
+
+
+def test_batched_tu_level_shapes(mh, ctx):
+    # sizes 64 u + r with u in 1..4, r in 1..63, offsets anywhere in 2048 parents
+    p, T = 65521, 64
+    NA = NB = NC = 2048
+    g = np.random.default_rng(5000)
+    A, B = parent_host(5001, p, NA), parent_host(5002, p, NB)
+    Cs = [parent_host(5100 + i, p, NC) for i in range(4)]
+    Ad, Bd = to_mh(mh, ctx, device_of(A), NA, T), to_mh(mh, ctx, device_of(B), NB, T)
+    Cds = [to_mh(mh, ctx, device_of(C), NC, T) for C in Cs]
+    calls = []
+    used = [[] for _ in range(4)]
+    while len(calls) < 32:
+        m, k, n = (64 * int(g.integers(1, 5)) + int(g.integers(1, 64)) for _ in range(3))
+        ci = len(calls) % 4
+        rc, cc = int(g.integers(0, NC - m + 1)), int(g.integers(0, NC - n + 1))
+        if any(not (rc + m <= r or r + mm <= rc or cc + n <= c or c + nn <= cc)
+               for r, c, mm, nn in used[ci]):
+            continue
+        used[ci].append((rc, cc, m, n))
+        calls.append(dict(ci=ci, rc=rc, cc=cc, m=m, k=k, n=n,
+                          ra=int(g.integers(0, NA - m + 1)), ca=int(g.integers(0, NA - k + 1)),
+                          rb=int(g.integers(0, NB - k + 1)), cb=int(g.integers(0, NB - n + 1))))
+    run_batch(mh, ctx, calls, A, B, Cs, Ad, Bd, Cds, NA, NB, NC, p, T, 2)
+
+
+def test_batched_degenerate_and_errors(mh, ctx):
+    torch = torch_cuda()
+    p, T, N = 65521, 32, 256
+    A, B, C = (parent_host(s, p, N) for s in (941, 942, 943))
+    Ad, Bd, Cd = (to_mh(mh, ctx, device_of(X), N, T) for X in (A, B, C))
+    assert mh.mh_matmul_modp_batched(ctx, None, 0, p, T, 2, stream_handle()) == 0
+    base = dict(C=Cd.data_ptr(), A=Ad.data_ptr(), B=Bd.data_ptr(), NC=N, NA=N, NB=N,
+                rc=0, cc=0, ra=0, ca=0, rb=0, cb=0)
+    # empty products are skipped; a real one alongside runs
+    calls = [dict(base, m=0, k=5, n=5), dict(base, m=5, k=0, n=5, rc=100),
+             dict(base, m=40, k=70, n=33, rc=200, cc=10, ra=3, ca=5, rb=7, cb=9)]
+    d = mh.make_descs(calls)
+    mh.check(mh.mh_matmul_modp_batched(ctx, d, 3, p, T, 2, stream_handle()))
+    want = expected_view(C, A, B, p, 200, 10, 3, 5, 7, 9, 40, 70, 33)
+    assert np.array_equal(host_of(to_cart(mh, ctx, Cd, N, T)), want)
+    # overlapping output blocks
+    d = mh.make_descs([dict(base, m=10, k=10, n=10), dict(base, m=10, k=10, n=10, rc=5, cc=5)])
+    assert mh.mh_matmul_modp_batched(ctx, d, 2, p, T, 2, 0) == mh.MH_E_ALIAS
+    # an output block over another product's input block
+    d = mh.make_descs([dict(base, m=10, k=10, n=10, rc=50),
+                       dict(base, A=Cd.data_ptr(), m=10, k=10, n=10, ra=55, rc=100)])
+    assert mh.mh_matmul_modp_batched(ctx, d, 2, p, T, 2, 0) == mh.MH_E_ALIAS
+    d = mh.make_descs([dict(base, m=10, k=10, n=10, rc=250)])
+    assert mh.mh_matmul_modp_batched(ctx, d, 1, p, T, 2, 0) == mh.MH_E_BOUNDS
+    assert mh.mh_matmul_modp_batched(ctx, d, 1, 1, T, 2, 0) == mh.MH_E_MODULUS
+    assert mh.mh_matmul_modp_batched(ctx, d, -1, p, T, 2, 0) == mh.MH_E_INVALID

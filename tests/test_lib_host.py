@@ -122,8 +122,8 @@ def test_limbs_and_kblock():
         s, info = describe(p=p, mode=mh.MH_MODE_LIMB_I8)
         assert s == 0 and info.limbs == L, p
         # |T_s| <= kblock * L * 2^14 must stay below 2^31
-        assert info.kblock * L * 2**14 < 2**31 and info.kblock % 32 == 0
-        assert (info.kblock + 32) * L * 2**14 >= 2**31
+        assert info.kblock * L * 2**14 < 2**31 and info.kblock % 64 == 0
+        assert (info.kblock + 64) * L * 2**14 >= 2**31
 
 
 # ------------------------------------------------------------------ planner
