@@ -113,6 +113,31 @@ mh_status mh_ctx_set_timing(mh_ctx *ctx, int enable);
 mh_status mh_ctx_kernel_time(mh_ctx *ctx, int kernel, double *total_ms, int64_t *launches,
                              int reset);
 
+/* Autotuning of the limb kernels' configuration (workgroup and wave tile,
+ * pipeline depth, LDS sharing) per shape bucket: single products by limbs,
+ * T and ceil(log2) of m, k, n; batches by limbs, T and ceil(log2) of their
+ * mean output area and mean k.  mode 0: built-in defaults; 1: use choices
+ * already in the context's cache; 2: as 1, and time every configuration on
+ * the first call of an uncached bucket (on the caller's operands, writing a
+ * scratch output, so C is unaffected; that call synchronises `stream`).
+ * Tuning runs the product once per configuration, so it should be enabled
+ * for representative calls, not for one-off products. */
+mh_status mh_ctx_set_autotune(mh_ctx *ctx, int mode);
+
+/* Configuration (MH_* kernel table index) cached for the single-product
+ * bucket of (p, T, m, k, n), or -1 in *cfg if none. */
+mh_status mh_ctx_tune_lookup(mh_ctx *ctx, uint32_t p, int32_t T, int64_t m, int64_t k,
+                             int64_t n, int32_t *cfg);
+
+/* Write the context's cache to a JSON file (tagged with the device name,
+ * CU count and HIP runtime version); replace it atomically. */
+mh_status mh_ctx_tune_cache_save(mh_ctx *ctx, const char *path);
+
+/* Merge the entries of a file written by mh_ctx_tune_cache_save for the same
+ * device tag into the context's cache; *loaded (may be null) is set to the
+ * number of entries taken.  MH_E_INVALID if the file cannot be read. */
+mh_status mh_ctx_tune_cache_load(mh_ctx *ctx, const char *path, int32_t *loaded);
+
 /* ------------------------------------------------------ host index math */
 
 /* Morton-hybrid index of Cartesian (i,j) for tile edge T (a power of two);

@@ -52,7 +52,8 @@ EXPORTS = (
     "mh_ctx_set_timing", "mh_ctx_kernel_time", "mh_encode", "mh_extract",
     "mh_classify_submatrix", "mh_layout_from_cartesian", "mh_layout_to_cartesian",
     "mh_matmul_modp", "mh_matmul_modp_batched", "mh_plan_describe", "mh_plan_leaves",
-    "mh_plan_gemm_tasks",
+    "mh_plan_gemm_tasks", "mh_ctx_set_autotune", "mh_ctx_tune_lookup", "mh_ctx_tune_cache_save",
+    "mh_ctx_tune_cache_load",
 )
 
 
@@ -100,6 +101,10 @@ def _load():
         "mh_ctx_set_timing": ([P, ct.c_int], ct.c_int),
         "mh_ctx_kernel_time": ([P, ct.c_int, ct.POINTER(ct.c_double), ct.POINTER(I64), ct.c_int],
                                ct.c_int),
+        "mh_ctx_set_autotune": ([P, ct.c_int], ct.c_int),
+        "mh_ctx_tune_lookup": ([P, U32, I32, I64, I64, I64, ct.POINTER(I32)], ct.c_int),
+        "mh_ctx_tune_cache_save": ([P, ct.c_char_p], ct.c_int),
+        "mh_ctx_tune_cache_load": ([P, ct.c_char_p, ct.POINTER(I32)], ct.c_int),
         "mh_encode": ([U64, U64, U32], U64),
         "mh_extract": ([U64, U32, ct.POINTER(U64), ct.POINTER(U64)], None),
         "mh_classify_submatrix": ([I64, I32, I64, I64, I64, I64, ct.POINTER(U32)], ct.c_int),
@@ -158,6 +163,27 @@ def mh_ctx_kernel_time(ctx: int, kernel: int, reset: bool = False) -> tuple[floa
     check(lib.mh_ctx_kernel_time(ctx, kernel, ct.byref(ms), ct.byref(n), 1 if reset else 0),
           "mh_ctx_kernel_time")
     return ms.value, n.value
+
+
+def mh_ctx_set_autotune(ctx: int, mode: int) -> int:
+    return lib.mh_ctx_set_autotune(ctx, mode)
+
+
+def mh_ctx_tune_lookup(ctx: int, p: int, T: int, m: int, k: int, n: int) -> int:
+    c = ct.c_int32()
+    check(lib.mh_ctx_tune_lookup(ctx, p, T, m, k, n, ct.byref(c)), "mh_ctx_tune_lookup")
+    return c.value
+
+
+def mh_ctx_tune_cache_save(ctx: int, path: str) -> int:
+    return lib.mh_ctx_tune_cache_save(ctx, path.encode())
+
+
+def mh_ctx_tune_cache_load(ctx: int, path: str) -> tuple[int, int]:
+    """Returns (status, entries loaded)."""
+    n = ct.c_int32()
+    s = lib.mh_ctx_tune_cache_load(ctx, path.encode(), ct.byref(n))
+    return s, n.value
 
 
 # ---------------------------------------------------------------- host math

@@ -168,6 +168,106 @@ void batched_release(mh_ctx *ctx)
 
 }  // namespace mh
 
+namespace mh {
+
+// Runs products already planned with kernel configuration cfg as one
+// batched graph on `stream`.  With c_override set, every output goes to that
+// buffer instead (tuning runs).
+mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int L, uint32_t p,
+                       hipStream_t stream, uint32_t *c_override)
+{
+    // Longest-processing-time order: every output block of a product costs
+    // its k, so products with the longest k go first.
+    std::vector<size_t> order(plans.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return plans[a].kpad > plans[b].kpad; });
+
+    // Panels of every product in the context workspace.
+    std::vector<size_t> aoff(plans.size()), boff(plans.size());
+    size_t total = 0;
+    for (size_t q = 0; q < plans.size(); ++q) {
+        const Plan &pl = plans[q];
+        const size_t nkb = size_t(pl.kpad / 32);
+        aoff[q] = total;
+        total += align256(size_t(pl.prow) * nkb * 32 * L);
+        boff[q] = total;
+        total += align256(size_t(pl.pcol) * nkb * 32 * L);
+    }
+    const int64_t ncalls = int64_t(plans.size());
+    mh_status s = ensure_queue(ctx, ncalls);
+    if (s != MH_OK) return s;
+    char *ws = (char *)workspace(ctx, total + 256);
+    if (!ws) return MH_E_NOMEM;
+    BatchedState &b = ctx->batched;
+
+    // The staging buffer may still be read by the previous batch's copy.
+    if (hipEventSynchronize(b.staging_free) != hipSuccess) return note_error(ctx, hipErrorUnknown);
+    const QueueView hq = queue_view(b.queue_host, b.queue_cap);
+    int64_t pack_total = 0, tile_total = 0;
+    for (int64_t q = 0; q < ncalls; ++q) {
+        const Plan &pl = plans[order[q]];
+        const Product &pr = pl.pr;
+        const int64_t nkb = pl.kpad / 32;
+        int8_t *Ap = (int8_t *)(ws + aoff[order[q]]);
+        int8_t *Bp = (int8_t *)(ws + boff[order[q]]);
+        PackTask &ta = hq.packs[2 * q];
+        PackTask &tb = hq.packs[2 * q + 1];
+        ta = PackTask{pr.A, Ap, pr.ra, pr.ca, pl.sr, pr.m, pr.k, pl.prow, nkb, 0, pr.logT};
+        tb = PackTask{pr.B, Bp, pr.rb, pr.cb, pl.sc, pr.n, pr.k, pl.pcol, nkb, 1, pr.logT};
+        hq.pack_prefix[2 * q] = pack_total;
+        pack_total += (pl.prow / 64) * ((nkb + 1) / 2);
+        hq.pack_prefix[2 * q + 1] = pack_total;
+        pack_total += (pl.pcol / 64) * ((nkb + 1) / 2);
+        LimbArgs &a = hq.calls[q];
+        std::memset(&a, 0, sizeof(a));
+        a.Ap = Ap;
+        a.Bp = Bp;
+        a.nkb = nkb;
+        a.kb_per_red = pl.kblock / 32;
+        a.C = c_override ? c_override : pr.C;
+        a.row0C = pl.row0C;
+        a.col0C = pl.col0C;
+        a.sr = pl.sr;
+        a.sc = pl.sc;
+        a.m = pr.m;
+        a.n = pr.n;
+        a.grid_m = pl.grid_m;
+        a.grid_n = pl.grid_n;
+        a.p = p;
+        a.mu = ~uint64_t(0) / p;
+        a.bias = ((uint64_t(1) << 31) + p - 1) / p * p;
+        a.pinv = 1.0 / double(p);
+        a.logT = pr.logT;
+        hq.tile_prefix[q] = tile_total;
+        tile_total += pl.grid_m * pl.grid_n;
+    }
+    hq.pack_prefix[2 * ncalls] = pack_total;
+    hq.tile_prefix[ncalls] = tile_total;
+    BatchHeader &h = *hq.hdr;
+    std::memset(&h, 0, sizeof(h));
+    h.npack = 2 * ncalls;
+    h.ncalls = ncalls;
+    h.pack_chunks = pack_total;
+    h.gemm_tiles = tile_total;
+    h.p = p;
+    h.L = L;
+
+    s = ensure_graph(ctx, cfg, L);
+    if (s != MH_OK) return s;
+    hipError_t e = hipMemcpyAsync(b.queue_dev, b.queue_host, queue_bytes(b.queue_cap),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(b.staging_free, stream);
+    if (e != hipSuccess) return note_error(ctx, e);
+    TimedLaunch t;
+    record_start(ctx, MH_K_BATCHED, stream, t);
+    e = hipGraphLaunch(b.exec, stream);
+    record_end(ctx, stream, t);
+    return note_error(ctx, e);
+}
+
+}  // namespace mh
+
 using namespace mh;
 
 extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, int32_t count,
@@ -238,95 +338,13 @@ extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, in
     const int L = limbs_for(p);
     std::vector<Plan> plans(live.size());
     for (size_t q = 0; q < live.size(); ++q) plan_product(prods[live[q]], MH_MODE_LIMB_I8, plans[q]);
-    const int cfg = batch_cfg(L, plans);
+    int cfg = -1;
+    if (ctx->autotune) {
+        cfg = tune_get(ctx, tune_key_batch(L, T, plans));
+        if (cfg < 0 && ctx->autotune == 2) cfg = tune_batch(ctx, plans, L, p, stream);
+    }
+    if (cfg < 0) cfg = batch_cfg(L, plans);
     for (size_t q = 0; q < live.size(); ++q)
         plan_product(prods[live[q]], MH_MODE_LIMB_I8, plans[q], cfg);
-    // Longest-processing-time order: every output block of a product costs
-    // its k, so products with the longest k go first.
-    std::vector<size_t> order(plans.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t a, size_t b) { return plans[a].kpad > plans[b].kpad; });
-
-    // Panels of every product in the context workspace.
-    std::vector<size_t> aoff(plans.size()), boff(plans.size());
-    size_t total = 0;
-    for (size_t q = 0; q < plans.size(); ++q) {
-        const Plan &pl = plans[q];
-        const size_t nkb = size_t(pl.kpad / 32);
-        aoff[q] = total;
-        total += align256(size_t(pl.prow) * nkb * 32 * L);
-        boff[q] = total;
-        total += align256(size_t(pl.pcol) * nkb * 32 * L);
-    }
-    const int64_t ncalls = int64_t(plans.size());
-    mh_status s = ensure_queue(ctx, ncalls);
-    if (s != MH_OK) return s;
-    char *ws = (char *)workspace(ctx, total + 256);
-    if (!ws) return MH_E_NOMEM;
-    BatchedState &b = ctx->batched;
-
-    // The staging buffer may still be read by the previous batch's copy.
-    if (hipEventSynchronize(b.staging_free) != hipSuccess) return note_error(ctx, hipErrorUnknown);
-    const QueueView hq = queue_view(b.queue_host, b.queue_cap);
-    int64_t pack_total = 0, tile_total = 0;
-    for (int64_t q = 0; q < ncalls; ++q) {
-        const Plan &pl = plans[order[q]];
-        const Product &pr = pl.pr;
-        const int64_t nkb = pl.kpad / 32;
-        int8_t *Ap = (int8_t *)(ws + aoff[order[q]]);
-        int8_t *Bp = (int8_t *)(ws + boff[order[q]]);
-        PackTask &ta = hq.packs[2 * q];
-        PackTask &tb = hq.packs[2 * q + 1];
-        ta = PackTask{pr.A, Ap, pr.ra, pr.ca, pl.sr, pr.m, pr.k, pl.prow, nkb, 0, pr.logT};
-        tb = PackTask{pr.B, Bp, pr.rb, pr.cb, pl.sc, pr.n, pr.k, pl.pcol, nkb, 1, pr.logT};
-        hq.pack_prefix[2 * q] = pack_total;
-        pack_total += (pl.prow / 64) * ((nkb + 1) / 2);
-        hq.pack_prefix[2 * q + 1] = pack_total;
-        pack_total += (pl.pcol / 64) * ((nkb + 1) / 2);
-        LimbArgs &a = hq.calls[q];
-        std::memset(&a, 0, sizeof(a));
-        a.Ap = Ap;
-        a.Bp = Bp;
-        a.nkb = nkb;
-        a.kb_per_red = pl.kblock / 32;
-        a.C = pr.C;
-        a.row0C = pl.row0C;
-        a.col0C = pl.col0C;
-        a.sr = pl.sr;
-        a.sc = pl.sc;
-        a.m = pr.m;
-        a.n = pr.n;
-        a.grid_m = pl.grid_m;
-        a.grid_n = pl.grid_n;
-        a.p = p;
-        a.mu = ~uint64_t(0) / p;
-        a.bias = ((uint64_t(1) << 31) + p - 1) / p * p;
-        a.pinv = 1.0 / double(p);
-        a.logT = pr.logT;
-        hq.tile_prefix[q] = tile_total;
-        tile_total += pl.grid_m * pl.grid_n;
-    }
-    hq.pack_prefix[2 * ncalls] = pack_total;
-    hq.tile_prefix[ncalls] = tile_total;
-    BatchHeader &h = *hq.hdr;
-    std::memset(&h, 0, sizeof(h));
-    h.npack = 2 * ncalls;
-    h.ncalls = ncalls;
-    h.pack_chunks = pack_total;
-    h.gemm_tiles = tile_total;
-    h.p = p;
-    h.L = L;
-
-    s = ensure_graph(ctx, cfg, L);
-    if (s != MH_OK) return s;
-    hipError_t e = hipMemcpyAsync(b.queue_dev, b.queue_host, queue_bytes(b.queue_cap),
-                                  hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipEventRecord(b.staging_free, stream);
-    if (e != hipSuccess) return note_error(ctx, e);
-    TimedLaunch t;
-    record_start(ctx, MH_K_BATCHED, stream, t);
-    e = hipGraphLaunch(b.exec, stream);
-    record_end(ctx, stream, t);
-    return note_error(ctx, e);
+    return launch_batch(ctx, plans, cfg, L, p, stream, nullptr);
 }

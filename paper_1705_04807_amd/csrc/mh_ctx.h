@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <string>
 #include <vector>
 
 #include "mh_internal.h"
@@ -43,6 +44,19 @@ bool outputs_alias(const Product &x, const Product &y);
 void batched_release(mh_ctx *ctx);
 mh_status run_plain(mh_ctx *ctx, const Plan &pl, hipStream_t s);
 mh_status run_limb(mh_ctx *ctx, const Plan &pl, hipStream_t s);
+mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int L, uint32_t p,
+                       hipStream_t stream, uint32_t *c_override);
+
+// Autotuner (mh_tune.cpp).
+struct TuneEntry {
+    int cfg;
+    double ms;
+};
+std::string tune_key_single(int L, const Product &p);
+std::string tune_key_batch(int L, int T, const std::vector<Plan> &plans);
+int tune_get(mh_ctx *ctx, const std::string &key);
+int tune_single(mh_ctx *ctx, const Product &p, hipStream_t s);
+int tune_batch(mh_ctx *ctx, std::vector<Plan> &plans, int L, uint32_t p, hipStream_t s);
 
 }  // namespace mh
 
@@ -56,4 +70,8 @@ struct mh_ctx {
     std::vector<hipEvent_t> event_pool;
     mh_status sticky = MH_OK;
     mh::BatchedState batched;
+    int autotune = 0;                          // 0 off, 1 cached choices, 2 tune on first use
+    std::map<std::string, mh::TuneEntry> tune; // shape bucket -> configuration
+    void *tune_scratch = nullptr;              // output parent for tuning runs
+    size_t tune_scratch_size = 0;
 };

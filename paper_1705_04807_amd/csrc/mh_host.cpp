@@ -142,6 +142,7 @@ extern "C" mh_status mh_ctx_destroy(mh_ctx *ctx)
         for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
         batched_release(ctx);
         if (ctx->ws) (void)hipFree(ctx->ws);
+        if (ctx->tune_scratch) (void)hipFree(ctx->tune_scratch);
     }
     delete ctx;
     return MH_OK;
@@ -720,5 +721,10 @@ extern "C" mh_status mh_matmul_modp(mh_ctx *ctx, uint32_t *C, int64_t NC, int64_
     plan_product(pr, mode, pl);
     DeviceGuard g(ctx->device);
     if (pl.mode == MH_MODE_PLAIN_U32) return run_plain(ctx, pl, stream);
+    if (ctx->autotune) {
+        int cfg = tune_get(ctx, tune_key_single(pl.L, pr));
+        if (cfg < 0 && ctx->autotune == 2) cfg = tune_single(ctx, pr, stream);
+        if (cfg >= 0) plan_product(pr, MH_MODE_LIMB_I8, pl, cfg);
+    }
     return run_limb(ctx, pl, stream);
 }
