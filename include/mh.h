@@ -22,7 +22,9 @@
  *
  * Conventions for every call below.
  *  - Matrix pointers are device pointers to uint32 words owned by the
- *    caller.  Entries must be residues in [0,p); this is not checked.
+ *    caller.  Entries must be residues in [0,p); this is not checked.  The
+ *    A and B parents of a product must be 16-byte aligned (hipMalloc gives
+ *    256), C 4-byte aligned (else MH_E_INVALID).
  *  - Arguments are validated synchronously before anything is enqueued; a
  *    call that returns an error has no effect.
  *  - Device calls are asynchronous on the caller's `stream` (0 = the null

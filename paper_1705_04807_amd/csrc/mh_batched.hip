@@ -34,7 +34,8 @@ int batch_cfg(int L, const std::vector<Plan> &plans)
     double area = 0.0;
     for (const Plan &p : plans) area += double(p.pr.m) * double(p.pr.n);
     area /= std::max<size_t>(plans.size(), 1);
-    int cfg = area <= 512.0 * 512.0 ? 6 : (L <= 2 ? 5 : 4);
+    // Small per-product tiles keep padding and tails low for uneven batches.
+    int cfg = (L <= 2 || area <= 512.0 * 512.0) ? 6 : 4;
     if (const char *e = std::getenv("MH_LIMB_CFG")) {  // explicit override (tuning runs)
         int c = std::atoi(e);
         if (c >= 0 && c < limb_cfg_count() && (2 * L - 1) * limb_cfg(c).wm * limb_cfg(c).wn <= 14)

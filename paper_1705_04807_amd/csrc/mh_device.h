@@ -36,6 +36,27 @@ __device__ __forceinline__ uint32_t mod_u64(uint64_t x, uint32_t p, uint64_t mu)
     return uint32_t(r);
 }
 
+// Largest i in [lo, n) with prefix[i] <= t, given prefix[lo] <= t < prefix[n]
+// (prefix non-decreasing).  A workgroup's popped work indices only grow, so
+// it searches forward from its previous answer: a galloping search costs
+// O(log distance) dependent loads instead of O(log n).
+__device__ __forceinline__ int64_t find_from(const int64_t *prefix, int64_t n, int64_t lo,
+                                             int64_t t)
+{
+    int64_t step = 1, hi = lo + 1;
+    while (hi < n && prefix[hi] <= t) {
+        lo = hi;
+        step <<= 1;
+        hi = lo + step;
+    }
+    if (hi > n) hi = n;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 // Workgroup id -> output tile (gm, gn).  Workgroups are dispatched to the
 // 8 XCDs round-robin; the first step gives each XCD a contiguous range of
 // logical tile ids so that the workgroups sharing one XCD's L2 also share

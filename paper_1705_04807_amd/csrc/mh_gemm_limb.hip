@@ -178,59 +178,62 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
         constexpr int NBLK = (WM * WAVES_M + WN * WAVES_N) * KS * L;
         const int wv = __builtin_amdgcn_readfirstlane(wave);
         const int64_t slabA0 = gm * (WM * WAVES_M), slabB0 = gn * (WN * WAVES_N);
-        const v4i *ga = reinterpret_cast<const v4i *>(a.Ap) + lane;
-        const v4i *gb = reinterpret_cast<const v4i *>(a.Bp) + lane;
+        // Block addresses are wave-uniform (scalar registers); only the lane's
+        // 16-byte offset is per lane.
+        const char *ga = reinterpret_cast<const char *>(a.Ap);
+        const char *gb = reinterpret_cast<const char *>(a.Bp);
+        const uint32_t lane_off = uint32_t(lane) * 16u;
         auto issue = [&](int64_t st, int buf) {
             const int64_t kb = st * KS;
             static_for<(NBLK + NW - 1) / NW>([&](auto r) {
                 const int b = wv + NW * r;
                 if (b < NBLK) {
-                    const v4i *src;
-                    if (b < NA) {
-                        const int sl = b / (KS * L), q = (b / L) % KS, t = b % L;
-                        src = ga + (((slabA0 + sl) * nkb + kb + q) * L + t) * 64;
-                    } else {
-                        const int bb = b - NA;
-                        const int sl = bb / (KS * L), q = (bb / L) % KS, t = bb % L;
-                        src = gb + (((slabB0 + sl) * nkb + kb + q) * L + t) * 64;
-                    }
+                    const bool isb = b >= NA;
+                    const int bb = isb ? b - NA : b;
+                    const int sl = bb / (KS * L), q = (bb / L) % KS, t = bb % L;
+                    const int64_t slab = (isb ? slabB0 : slabA0) + sl;
+                    const char *blk = (isb ? gb : ga) + (((slab * nkb + kb + q) * L + t) << 10);
                     __builtin_amdgcn_global_load_lds(
-                        src, (__attribute__((address_space(3))) void *)(lds_buf + (buf * NBLK + b) * 64),
+                        blk + lane_off,
+                        (__attribute__((address_space(3))) void *)(lds_buf + (buf * NBLK + b) * 64),
                         16, 0, 0);
                 }
             });
         };
         const int64_t nst = nkb / KS, st_red = a.kb_per_red / KS;
         issue(0, 0);
-        for (int64_t st = 0; st < nst; ++st) {
-            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's blocks of stage st landed
-            __syncthreads();                     // every wave's did; buffer (st+1)&1 is free again
-            if (st + 1 < nst) issue(st + 1, int((st + 1) & 1));
-            const v4i *sb = lds_buf + (st & 1) * (NBLK * 64) + lane;
-            static_for<KS>([&](auto q) {
-                v4i fa[WM][L], fb[WN][L];
-                static_for<WM>([&](auto i) {
+        for (int64_t st0 = 0; st0 < nst; st0 += st_red) {
+            const int64_t st1 = (st0 + st_red < nst) ? st0 + st_red : nst;
+            for (int64_t st = st0; st < st1; ++st) {
+                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's blocks of stage st landed
+                __syncthreads();                     // every wave's did; buffer (st+1)&1 is free again
+                if (st + 1 < nst) issue(st + 1, int((st + 1) & 1));
+                const v4i *sb = lds_buf + (st & 1) * (NBLK * 64) + lane;
+                static_for<KS>([&](auto q) {
+                    v4i fa[WM][L], fb[WN][L];
+                    static_for<WM>([&](auto i) {
+                        static_for<L>([&](auto t) {
+                            fa[i][t] = sb[(((wmi * WM + i) * KS + q) * L + t) * 64];
+                        });
+                    });
+                    static_for<WN>([&](auto j) {
+                        static_for<L>([&](auto u) {
+                            fb[j][u] = sb[(NA + ((wni * WN + j) * KS + q) * L + u) * 64];
+                        });
+                    });
                     static_for<L>([&](auto t) {
-                        fa[i][t] = sb[(((wmi * WM + i) * KS + q) * L + t) * 64];
-                    });
-                });
-                static_for<WN>([&](auto j) {
-                    static_for<L>([&](auto u) {
-                        fb[j][u] = sb[(NA + ((wni * WN + j) * KS + q) * L + u) * 64];
-                    });
-                });
-                static_for<L>([&](auto t) {
-                    static_for<L>([&](auto u) {
-                        static_for<WM>([&](auto i) {
-                            static_for<WN>([&](auto j) {
-                                acc[t + u][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                    fa[i][t], fb[j][u], acc[t + u][i][j], 0, 0, 0);
+                        static_for<L>([&](auto u) {
+                            static_for<WM>([&](auto i) {
+                                static_for<WN>([&](auto j) {
+                                    acc[t + u][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                        fa[i][t], fb[j][u], acc[t + u][i][j], 0, 0, 0);
+                                });
                             });
                         });
                     });
                 });
-            });
-            if ((st + 1) % st_red == 0 || st + 1 == nst) flush();
+            }
+            flush();
         }
     }
 }
@@ -246,7 +249,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb(LimbArgs a
 // Persistent form for a batch of products: every workgroup pops output
 // blocks from the queue through an atomic counter until none is left (the
 // exit test is the same for all waves of the group).  Blocks are numbered
-// call by call in the queue's order (largest k first); a binary search over
+// call by call in the queue's order (largest k first); a forward search over
 // the per-call prefix sums finds the call of a block.
 template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb_batched(QueueView q,
@@ -255,17 +258,14 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb_batched(Qu
     __shared__ int64_t task_s;
     const int64_t total = q.hdr->gemm_tiles;
     const int64_t ncalls = q.hdr->ncalls;
+    int64_t lo = 0;
     for (;;) {
         if (threadIdx.x == 0) task_s = int64_t(atomicAdd((unsigned long long *)counter, 1ull));
         __syncthreads();
         const int64_t t = task_s;
         __syncthreads();
         if (t >= total) break;
-        int64_t lo = 0, hi = ncalls;  // tile_prefix[lo] <= t < tile_prefix[hi]
-        while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (q.tile_prefix[mid] <= t) lo = mid; else hi = mid;
-        }
+        lo = find_from(q.tile_prefix, ncalls, lo, t);
         const LimbArgs a = q.calls[lo];
         const int64_t local = t - q.tile_prefix[lo];
         gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS>(a, local / a.grid_n, local % a.grid_n);

@@ -304,6 +304,9 @@ mh_status validate_product(const Product &p, bool need_ptrs)
     if (p.rb + p.k > p.NB || p.cb + p.n > p.NB) return MH_E_BOUNDS;
     if (p.p < 2u || p.p > 0x7FFFFFFFu) return MH_E_MODULUS;
     if (need_ptrs && (!p.C || !p.A || !p.B)) return MH_E_INVALID;
+    // A and B are read with 16-byte loads, C with 4-byte ones.
+    if (need_ptrs && (((uintptr_t)p.A & 15) || ((uintptr_t)p.B & 15) || ((uintptr_t)p.C & 3)))
+        return MH_E_INVALID;
     if (need_ptrs) {
         if (output_aliases(p.C, p.NC, p.rc, p.cc, p.m, p.n, p.A, p.NA, p.ra, p.ca, p.m, p.k))
             return MH_E_ALIAS;

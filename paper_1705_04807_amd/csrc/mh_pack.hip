@@ -98,32 +98,57 @@ __device__ __forceinline__ void pack_chunk(int8_t *__restrict__ dst, int64_t nkb
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
-    if (!TRANS) {
-        // lanes walk the depth (source columns, contiguous inside a tile row)
-        const int64_t kap = kap0 + lane;
-        const bool kok = kap < K;
-        const uint64_t cpart = col_part(uint64_t(c0 + kap), logT);
-#pragma unroll 4
-        for (int i = 0; i < kChunk / 4; ++i) {
-            const int rr = wave + 4 * i;
-            const int64_t rho = rho0 + rr;
-            uint32_t v = 0;
-            if (kok && rho >= shift && rho < shift + R)
-                v = src[row_part(uint64_t(r0 + rho - shift), logT) | cpart];
-            tile[rr * kLdsStride + lane] = v;
-        }
-    } else {
-        // lanes walk the panel rows (source columns, contiguous inside a tile row)
-        const int64_t rho = rho0 + lane;
-        const bool rok = rho >= shift && rho < shift + R;
-        const uint64_t cpart = col_part(uint64_t(c0 + rho - shift), logT);
-#pragma unroll 4
-        for (int i = 0; i < kChunk / 4; ++i) {
-            const int kk = wave + 4 * i;
-            const int64_t kap = kap0 + kk;
-            uint32_t v = 0;
-            if (rok && kap < K) v = src[row_part(uint64_t(r0 + kap), logT) | cpart];
-            tile[lane * kLdsStride + kk] = v;
+    // The chunk's source rectangle is read as aligned 16-byte groups: a
+    // window of 17 groups (68 words) along the contiguous source direction
+    // covers the 64 needed words whatever their alignment.  An aligned group
+    // never crosses a tile row (T is a multiple of 4), so each group is one
+    // contained piece; groups wholly outside the block are not read (they may
+    // lie beyond the parent), and words outside it are stored as zero.
+    //   !TRANS: contiguous direction = depth kap (source column c0 + kap),
+    //           other direction = panel row rho (source row r0 + rho - shift).
+    //   TRANS:  contiguous direction = panel row rho (source column
+    //           c0 + rho - shift), other = depth kap (source row r0 + kap).
+    {
+        const int64_t cfirst = TRANS ? c0 + rho0 - shift : c0 + kap0;  // source col of slot 0
+        const int64_t clo = TRANS ? c0 : c0;                            // block's columns:
+        const int64_t chi = TRANS ? c0 + R : c0 + K;                    //   [clo, chi)
+        const int64_t gbase = cfirst & ~int64_t(3);
+        const int mis = int(cfirst - gbase);
+        constexpr int G = 17;
+#pragma unroll
+        for (int q = 0; q < (kChunk * G + 255) / 256; ++q) {
+            const int gi = int(threadIdx.x) + 256 * q;
+            if (gi >= kChunk * G) break;
+            const int other = gi / G, g = gi - other * G;
+            const int64_t gcol = gbase + 4 * g;
+            int64_t srow;
+            bool ok;
+            if (!TRANS) {
+                const int64_t rho = rho0 + other;
+                ok = rho >= shift && rho < shift + R;
+                srow = r0 + rho - shift;
+            } else {
+                const int64_t kap = kap0 + other;
+                ok = kap < K;
+                srow = r0 + kap;
+            }
+            ok = ok && gcol + 4 > clo && gcol < chi;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (ok)
+                v = *reinterpret_cast<const uint4 *>(
+                    src + (row_part(uint64_t(srow), logT) | col_part(uint64_t(gcol), logT)));
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int slot = 4 * g + e - mis;  // position along the contiguous direction
+                const int64_t col = gcol + e;
+                if (slot < 0 || slot >= kChunk) continue;
+                const uint32_t x = (col >= clo && col < chi) ? w[e] : 0u;
+                if (!TRANS)
+                    tile[other * kLdsStride + slot] = ok ? x : 0u;
+                else
+                    tile[slot * kLdsStride + other] = ok ? x : 0u;
+            }
         }
     }
     __syncthreads();
@@ -161,41 +186,45 @@ __global__ __launch_bounds__(256) void k_pack_limb(int8_t *__restrict__ dst, int
                          int64_t(blockIdx.y) * kChunk, int64_t(blockIdx.x) * kChunk, tile);
 }
 
-// Persistent form for a batch: workgroups pop 64 x 64 chunks of all the
-// operand panels of the batch through an atomic counter; a binary search
-// over the per-operand prefix sums finds the operand of a chunk.  The
-// barrier after reading the popped index also orders the LDS reuse between
-// consecutive chunks.
+// Persistent form for a batch: workgroups pop runs of 64 x 64 chunks of all
+// the operand panels of the batch through an atomic counter; a forward search
+// over the per-operand prefix sums finds the operand of a run's first chunk,
+// and the following chunks step forward from it.  Barriers between chunks
+// (and after reading the popped index) order the reuse of the LDS tile.
 template <int L>
 __global__ __launch_bounds__(256) void k_pack_limb_batched(QueueView q, uint64_t *counter)
 {
+    constexpr int64_t kGrab = 8;  // chunks per pop: one atomic and one search per 8 chunks
     __shared__ uint32_t tile[kChunk * kLdsStride];
     __shared__ int64_t chunk_s;
     const int64_t total = q.hdr->pack_chunks;
     const int64_t npack = q.hdr->npack;
     const uint32_t p = q.hdr->p;
     const int32_t H = int32_t(limb_threshold(L));
+    int64_t lo = 0;
     for (;;) {
-        if (threadIdx.x == 0) chunk_s = int64_t(atomicAdd((unsigned long long *)counter, 1ull));
+        if (threadIdx.x == 0)
+            chunk_s = int64_t(atomicAdd((unsigned long long *)counter, (unsigned long long)kGrab));
         __syncthreads();
-        const int64_t c = chunk_s;
+        const int64_t c0 = chunk_s;
         __syncthreads();
-        if (c >= total) break;
-        int64_t lo = 0, hi = npack;  // pack_prefix[lo] <= c < pack_prefix[hi]
-        while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (q.pack_prefix[mid] <= c) lo = mid; else hi = mid;
+        if (c0 >= total) break;
+        lo = find_from(q.pack_prefix, npack, lo, c0);
+        const int64_t c1 = c0 + kGrab < total ? c0 + kGrab : total;
+        for (int64_t c = c0; c < c1; ++c) {
+            while (q.pack_prefix[lo + 1] <= c) ++lo;  // the next chunks may start the next operand
+            const PackTask t = q.packs[lo];
+            const int64_t local = c - q.pack_prefix[lo];
+            const int64_t kchunks = (t.nkb + 1) / 2;
+            const int64_t rho0 = (local / kchunks) * kChunk, kap0 = (local % kchunks) * kChunk;
+            if (c > c0) __syncthreads();  // the previous chunk's LDS reads are done
+            if (t.trans)
+                pack_chunk<L, true>(t.dst, t.nkb, t.src, t.r0, t.c0, t.shift, t.R, t.K, t.logT, p,
+                                    H, rho0, kap0, tile);
+            else
+                pack_chunk<L, false>(t.dst, t.nkb, t.src, t.r0, t.c0, t.shift, t.R, t.K, t.logT, p,
+                                     H, rho0, kap0, tile);
         }
-        const PackTask t = q.packs[lo];
-        const int64_t local = c - q.pack_prefix[lo];
-        const int64_t kchunks = (t.nkb + 1) / 2;
-        const int64_t rho0 = (local / kchunks) * kChunk, kap0 = (local % kchunks) * kChunk;
-        if (t.trans)
-            pack_chunk<L, true>(t.dst, t.nkb, t.src, t.r0, t.c0, t.shift, t.R, t.K, t.logT, p, H,
-                                rho0, kap0, tile);
-        else
-            pack_chunk<L, false>(t.dst, t.nkb, t.src, t.r0, t.c0, t.shift, t.R, t.K, t.logT, p, H,
-                                 rho0, kap0, tile);
     }
 }
 

@@ -189,6 +189,10 @@ def test_alias_rejected(mh, ctx):
                              0, 0, 4, 4, 4, 1, 32, 1, 0) == mh.MH_E_MODULUS
     assert mh.mh_matmul_modp(ctx, d, 256, 250, 0, Y.data_ptr(), 256, 0, 0, Y.data_ptr(), 256,
                              0, 0, 8, 4, 4, 65521, 32, 1, 0) == mh.MH_E_BOUNDS
+    # A parent not 16-byte aligned
+    Z = torch.zeros(256 * 256 + 4, dtype=torch.int32, device="cuda")
+    assert mh.mh_matmul_modp(ctx, d, 256, 0, 0, Z.data_ptr() + 4, 256, 0, 0, Y.data_ptr(), 256,
+                             0, 0, 4, 4, 4, 65521, 32, 2, 0) == mh.MH_E_INVALID
 
 
 @MODES
