@@ -70,13 +70,19 @@ enum {
                           range [alpha, alpha + lambda) */
 };
 
-/* Arithmetic forms of the product.  All are exact; they differ in speed. */
+/* Arithmetic forms of the product (the low byte of `mode`).  All are exact;
+ * they differ in speed and in the moduli they accept. */
 enum {
     MH_MODE_AUTO = 0,      /* pick by shape */
     MH_MODE_PLAIN_U32 = 1, /* VALU kernel, 64-bit multiply-accumulate with carry word */
     MH_MODE_LIMB_I8 = 2    /* residues split into signed 8-bit limbs; int8 MFMA with
                               int32 accumulators; mod-p reduction once per k-block */
 };
+
+/* Or-ed into `mode`: subtractive update C := (C - A.B) mod p, the Schur
+ * complement step of an LU / TU elimination (the caller side of section 1's
+ * TU recursion). */
+#define MH_SUBTRACT 0x100
 
 /* Kernel classes reported by mh_ctx_kernel_time. */
 enum {

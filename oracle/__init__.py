@@ -50,6 +50,8 @@ def lib():
         U64 = ct.c_uint64
         L.oracle_matmul_modp.argtypes = [P, I64, P, I64, P, I64, I64, I64, I64, U32, ct.c_int]
         L.oracle_matmul_modp.restype = None
+        L.oracle_matmul_modp_sub.argtypes = [P, I64, P, I64, P, I64, I64, I64, I64, U32, ct.c_int]
+        L.oracle_matmul_modp_sub.restype = None
         L.oracle_matmul_modp_entries.argtypes = [P, P, P, I64, P, I64, P, I64, P, I64, I64,
                                                  U32, ct.c_int]
         L.oracle_matmul_modp_entries.restype = None
@@ -99,10 +101,23 @@ def matmul_modp(C: np.ndarray, A: np.ndarray, B: np.ndarray, p: int,
                              nthreads or default_threads())
 
 
+def matmul_modp_sub(C: np.ndarray, A: np.ndarray, B: np.ndarray, p: int,
+                    nthreads: int | None = None) -> None:
+    """In place: C <- (C - A @ B) mod p on 2-D uint32 arrays."""
+    _u32(C), _u32(A), _u32(B)
+    m, k = A.shape
+    k2, n = B.shape
+    assert k == k2 and C.shape == (m, n)
+    lib().oracle_matmul_modp_sub(_ptr(C), n, _ptr(A), k, _ptr(B), n, m, k, n, p,
+                                 nthreads or default_threads())
+
+
 def matmul_modp_view(C: np.ndarray, A: np.ndarray, B: np.ndarray, p: int,
                      rc: int, cc: int, ra: int, ca: int, rb: int, cb: int,
-                     m: int, k: int, n: int, nthreads: int | None = None) -> None:
-    """In place on whole Cartesian parents: C[rc:rc+m, cc:cc+n] += A[ra.., ca..] B[rb.., cb..]."""
+                     m: int, k: int, n: int, nthreads: int | None = None,
+                     subtract: bool = False) -> None:
+    """In place on whole Cartesian parents: C[rc:rc+m, cc:cc+n] += A[ra.., ca..] B[rb.., cb..]
+    (or -= with subtract)."""
     _u32(C), _u32(A), _u32(B)
     if m <= 0 or n <= 0:
         return
@@ -111,9 +126,9 @@ def matmul_modp_view(C: np.ndarray, A: np.ndarray, B: np.ndarray, p: int,
     assert ra + m <= A.shape[0] and ca + k <= lda
     assert rb + k <= B.shape[0] and cb + n <= ldb
     base = lambda X, r, c, ld: ct.c_void_p(X.ctypes.data + 4 * (r * ld + c))
-    lib().oracle_matmul_modp(base(C, rc, cc, ldc), ldc, base(A, ra, ca, lda), lda,
-                             base(B, rb, cb, ldb), ldb, m, k, n, p,
-                             nthreads or default_threads())
+    fn = lib().oracle_matmul_modp_sub if subtract else lib().oracle_matmul_modp
+    fn(base(C, rc, cc, ldc), ldc, base(A, ra, ca, lda), lda, base(B, rb, cb, ldb), ldb, m, k, n,
+       p, nthreads or default_threads())
 
 
 def matmul_modp_entries(rows, cols, C: np.ndarray, A: np.ndarray, B: np.ndarray, p: int,

@@ -16,6 +16,7 @@
  *
  * Contents
  *   oracle_matmul_modp          the definition of the product (Cartesian)
+ *   oracle_matmul_modp_sub      the subtractive update C - A.B mod p
  *   oracle_matmul_modp_entries  the same definition, for chosen entries only
  *   oracle_freivalds            Freivalds' randomised product check
  *   oracle_mh_encode/_extract   Morton-hybrid index by walking the quadrant
@@ -67,6 +68,37 @@ void oracle_matmul_modp(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda
             for (int64_t j = 0; j < n; ++j) {
                 u128 s = acc[j] + (u128)C[i * ldc + j];
                 C[i * ldc + j] = (uint32_t)(s % p);
+            }
+        }
+        free(acc);
+    }
+}
+
+/*
+ * The subtractive update C[i][j] <- (C[i][j] - sum_l A[i][l] B[l][j]) mod p,
+ * the Schur complement step of an elimination.  The sum is reduced mod p
+ * first, then subtracted as (C + p - s) mod p.
+ */
+void oracle_matmul_modp_sub(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda,
+                            const uint32_t *B, int64_t ldb, int64_t m, int64_t k, int64_t n,
+                            uint32_t p, int nthreads)
+{
+    if (m <= 0 || n <= 0) return;
+    if (nthreads <= 0) nthreads = 1;
+#pragma omp parallel num_threads(nthreads)
+    {
+        u128 *acc = (u128 *)malloc(sizeof(u128) * (size_t)n);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < m; ++i) {
+            for (int64_t j = 0; j < n; ++j) acc[j] = 0;
+            for (int64_t l = 0; l < k; ++l) {
+                uint64_t a = A[i * lda + l];
+                const uint32_t *brow = B + l * ldb;
+                for (int64_t j = 0; j < n; ++j) acc[j] += (u128)(a * (uint64_t)brow[j]);
+            }
+            for (int64_t j = 0; j < n; ++j) {
+                uint64_t s = (uint64_t)(acc[j] % p);
+                C[i * ldc + j] = (uint32_t)(((uint64_t)C[i * ldc + j] + p - s) % p);
             }
         }
         free(acc);

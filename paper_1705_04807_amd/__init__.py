@@ -37,6 +37,7 @@ MH_QUADRANT = 4
 MH_MODE_AUTO = 0
 MH_MODE_PLAIN_U32 = 1
 MH_MODE_LIMB_I8 = 2
+MH_SUBTRACT = 0x100
 
 MH_K_LAYOUT_FROM = 0
 MH_K_LAYOUT_TO = 1

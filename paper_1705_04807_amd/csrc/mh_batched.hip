@@ -214,8 +214,9 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
         int8_t *Bp = (int8_t *)(ws + boff[order[q]]);
         PackTask &ta = hq.packs[2 * q];
         PackTask &tb = hq.packs[2 * q + 1];
-        ta = PackTask{pr.A, Ap, pr.ra, pr.ca, pl.sr, pr.m, pr.k, pl.prow, nkb, 0, pr.logT};
-        tb = PackTask{pr.B, Bp, pr.rb, pr.cb, pl.sc, pr.n, pr.k, pl.pcol, nkb, 1, pr.logT};
+        ta = PackTask{pr.A, Ap, pr.ra, pr.ca, pl.sr, pr.m, pr.k, pl.prow, nkb, 0, pr.logT, 0, 0};
+        tb = PackTask{pr.B, Bp, pr.rb, pr.cb, pl.sc, pr.n, pr.k, pl.pcol, nkb, 1, pr.logT,
+                      pl.sub ? 1 : 0, 0};
         hq.pack_prefix[2 * q] = pack_total;
         pack_total += (pl.prow / 64) * ((nkb + 1) / 2);
         hq.pack_prefix[2 * q + 1] = pack_total;
@@ -276,7 +277,10 @@ extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, in
                                             hipStream_t stream)
 {
     if (!ctx || count < 0 || (count > 0 && !d)) return MH_E_INVALID;
-    if (mode < MH_MODE_AUTO || mode > MH_MODE_LIMB_I8) return MH_E_UNSUPPORTED;
+    int form;
+    bool sub;
+    if (!parse_mode(mode, form, sub)) return MH_E_UNSUPPORTED;
+    mode = form;
     if (!valid_T(T)) return MH_E_UNSUPPORTED;
     if (p < 2u || p > 0x7FFFFFFFu) return MH_E_MODULUS;
     // Validate every product first: a failing call has no effect.
@@ -330,6 +334,7 @@ extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, in
         for (int32_t i : live) {
             Plan pl;
             plan_product(prods[i], MH_MODE_PLAIN_U32, pl);
+            pl.sub = sub;
             mh_status s = run_plain(ctx, pl, stream);
             if (s != MH_OK) return s;
         }
@@ -345,7 +350,9 @@ extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, in
         if (cfg < 0 && ctx->autotune == 2) cfg = tune_batch(ctx, plans, L, p, stream);
     }
     if (cfg < 0) cfg = batch_cfg(L, plans);
-    for (size_t q = 0; q < live.size(); ++q)
+    for (size_t q = 0; q < live.size(); ++q) {
         plan_product(prods[live[q]], MH_MODE_LIMB_I8, plans[q], cfg);
+        plans[q].sub = sub;
+    }
     return launch_batch(ctx, plans, cfg, L, p, stream, nullptr);
 }

@@ -133,7 +133,8 @@ __global__ __launch_bounds__(256) void k_gemm_plain(PlainArgs a)
             const uint64_t hpart = uint64_t(mod_u64(hi[i][j], a.p, a.mu)) * r64;
             const uint32_t r = mod_u64(uint64_t(mod_u64(lo[i][j], a.p, a.mu)) + hpart, a.p, a.mu);
             const uint64_t off = mh_offset(uint64_t(a.row0C + rho), uint64_t(a.col0C + gam), a.logT);
-            uint32_t c = a.C[off] + r;
+            const uint32_t add = a.sub ? (r ? a.p - r : 0u) : r;  // C - r = C + (p - r)
+            uint32_t c = a.C[off] + add;
             if (c >= a.p) c -= a.p;
             a.C[off] = c;
         }

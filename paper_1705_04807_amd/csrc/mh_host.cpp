@@ -355,6 +355,7 @@ void segments(int64_t len, int64_t offA, int64_t offB, int32_t T, std::vector<in
 void plan_product(const Product &p, int mode, Plan &pl, int forced_cfg)
 {
     pl.pr = p;
+    pl.sub = false;
     const int64_t T = p.T;
     if (mode == MH_MODE_AUTO) {
         double work = double(p.m) * double(p.n) * double(p.k);
@@ -441,7 +442,10 @@ extern "C" mh_status mh_plan_describe(int64_t NC, int64_t rc, int64_t cc, int64_
                                       mh_plan_info *out)
 {
     if (!out) return MH_E_INVALID;
-    if (mode < MH_MODE_AUTO || mode > MH_MODE_LIMB_I8) return MH_E_UNSUPPORTED;
+    int form;
+    bool sub;
+    if (!parse_mode(mode, form, sub)) return MH_E_UNSUPPORTED;
+    mode = form;
     Product pr = make_product(nullptr, NC, rc, cc, nullptr, NA, ra, ca, nullptr, NB, rb, cb, m,
                               k, n, p, T);
     mh_status s = validate_product(pr, false);
@@ -516,7 +520,10 @@ extern "C" mh_status mh_plan_gemm_tasks(int64_t NC, int64_t rc, int64_t cc, int6
                                         int64_t *count)
 {
     if (!count || (cap > 0 && !out)) return MH_E_INVALID;
-    if (mode < MH_MODE_AUTO || mode > MH_MODE_LIMB_I8) return MH_E_UNSUPPORTED;
+    int form;
+    bool sub;
+    if (!parse_mode(mode, form, sub)) return MH_E_UNSUPPORTED;
+    mode = form;
     Product pr = make_product(nullptr, NC, rc, cc, nullptr, NA, ra, ca, nullptr, NB, rb, cb, m,
                               k, n, p, T);
     mh_status s = validate_product(pr, false);
@@ -619,6 +626,7 @@ mh_status run_plain(mh_ctx *ctx, const Plan &pl, hipStream_t s)
     a.p = p.p;
     a.mu = barrett_mu(p.p);
     a.logT = p.logT;
+    a.sub = pl.sub ? 1 : 0;
     if (pl.in_place) {
         a.A = p.A;
         a.B = p.B;
@@ -673,11 +681,12 @@ mh_status run_limb(mh_ctx *ctx, const Plan &pl, hipStream_t s)
     int8_t *Bp = (int8_t *)(ws + ((abytes + 255) & ~size_t(255)));
     TimedLaunch t;
     record_start(ctx, MH_K_PACK, s, t);
-    hipError_t e = launch_pack_limb(Ap, pl.prow, nkb, p.A, p.ra, p.ca, pl.sr, p.m, p.k, 0,
+    hipError_t e = launch_pack_limb(Ap, pl.prow, nkb, p.A, p.ra, p.ca, pl.sr, p.m, p.k, 0, 0,
                                     p.logT, p.p, L, s);
+    // C - A.B = C + A.(-B): the subtractive update negates B while packing it.
     if (e == hipSuccess)
-        e = launch_pack_limb(Bp, pl.pcol, nkb, p.B, p.rb, p.cb, pl.sc, p.n, p.k, 1, p.logT, p.p,
-                             L, s);
+        e = launch_pack_limb(Bp, pl.pcol, nkb, p.B, p.rb, p.cb, pl.sc, p.n, p.k, 1,
+                             pl.sub ? 1 : 0, p.logT, p.p, L, s);
     record_end(ctx, s, t);
     if (e != hipSuccess) return note_error(ctx, e);
     LimbArgs a;
@@ -715,19 +724,23 @@ extern "C" mh_status mh_matmul_modp(mh_ctx *ctx, uint32_t *C, int64_t NC, int64_
                                     int32_t mode, hipStream_t stream)
 {
     if (!ctx) return MH_E_INVALID;
-    if (mode < MH_MODE_AUTO || mode > MH_MODE_LIMB_I8) return MH_E_UNSUPPORTED;
+    int form;
+    bool sub;
+    if (!parse_mode(mode, form, sub)) return MH_E_UNSUPPORTED;
     Product pr = make_product(C, NC, rc, cc, A, NA, ra, ca, B, NB, rb, cb, m, k, n, p, T);
     mh_status s = validate_product(pr, true);
     if (s != MH_OK) return s;
     if (m == 0 || n == 0 || k == 0) return MH_OK;
     Plan pl;
-    plan_product(pr, mode, pl);
+    plan_product(pr, form, pl);
+    pl.sub = sub;
     DeviceGuard g(ctx->device);
     if (pl.mode == MH_MODE_PLAIN_U32) return run_plain(ctx, pl, stream);
     if (ctx->autotune) {
         int cfg = tune_get(ctx, tune_key_single(pl.L, pr));
         if (cfg < 0 && ctx->autotune == 2) cfg = tune_single(ctx, pr, stream);
         if (cfg >= 0) plan_product(pr, MH_MODE_LIMB_I8, pl, cfg);
+        pl.sub = sub;
     }
     return run_limb(ctx, pl, stream);
 }

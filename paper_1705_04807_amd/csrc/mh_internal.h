@@ -163,6 +163,7 @@ struct Plan {
     bool in_place;           // plain mode reads A and B tiles in the parents
     int64_t sk;              // plain in-place: k shift (ca mod T)
     int limb_cfg;            // index into the limb kernel table
+    bool sub;                // C := C - A.B (B is negated while packing)
 };
 
 // ------------------------------------------------------ host prototypes
@@ -172,6 +173,14 @@ int log2i(int64_t x);
 mh_status check_parent(int64_t N, int32_t T);
 mh_status validate_product(const Product &p, bool need_ptrs);
 void plan_product(const Product &p, int mode, Plan &out, int forced_cfg = -1);
+
+// mode argument of the ABI: arithmetic form in the low byte, MH_SUBTRACT flag.
+inline bool parse_mode(int32_t mode, int &form, bool &sub)
+{
+    form = mode & 0xFF;
+    sub = (mode & MH_SUBTRACT) != 0;
+    return (mode & ~(0xFF | MH_SUBTRACT)) == 0 && form >= MH_MODE_AUTO && form <= MH_MODE_LIMB_I8;
+}
 void segments(int64_t len, int64_t offA, int64_t offB, int32_t T, std::vector<int64_t> &cuts);
 
 // limb kernel table
@@ -200,7 +209,7 @@ hipError_t launch_pack_u32(uint32_t *dst, int64_t prow, int64_t pcol, const uint
 // shift+R) or depths [0,K) are zero.
 hipError_t launch_pack_limb(int8_t *dst, int64_t prow, int64_t nkb, const uint32_t *src,
                             int64_t r0, int64_t c0, int64_t shift, int64_t R, int64_t K,
-                            int trans, int logT, uint32_t p, int L, hipStream_t s);
+                            int trans, int neg, int logT, uint32_t p, int L, hipStream_t s);
 
 struct PlainArgs {
     const uint32_t *A;   // MH parent (in place) or tile-major panel
@@ -216,6 +225,7 @@ struct PlainArgs {
     uint32_t p;
     uint64_t mu;         // floor((2^64 - 1) / p)
     int logT;
+    int sub;             // C := C - A.B
 };
 hipError_t launch_gemm_plain(const PlainArgs &a, hipStream_t s);
 
@@ -247,6 +257,7 @@ struct PackTask {
     int8_t *dst;
     int64_t r0, c0, shift, R, K, prow, nkb;
     int32_t trans, logT;
+    int32_t neg, pad;   // neg: pack (p - x) mod p
 };
 
 struct BatchHeader {

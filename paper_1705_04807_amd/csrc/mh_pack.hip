@@ -94,7 +94,7 @@ __device__ __forceinline__ void pack_chunk(int8_t *__restrict__ dst, int64_t nkb
                                            const uint32_t *__restrict__ src, int64_t r0,
                                            int64_t c0, int64_t shift, int64_t R, int64_t K,
                                            int logT, uint32_t p, int32_t H, int64_t rho0,
-                                           int64_t kap0, uint32_t *tile)
+                                           int64_t kap0, uint32_t *tile, int neg)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
@@ -167,6 +167,10 @@ __device__ __forceinline__ void pack_chunk(int8_t *__restrict__ dst, int64_t nkb
         x[4 * q + 2] = v.z;
         x[4 * q + 3] = v.w;
     }
+    if (neg) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) x[e] = x[e] ? p - x[e] : 0u;  // (p - x) mod p
+    }
     uint4 d[L];
     digits16<L>(x, p, H, d);
     const int64_t slab = rho0 / 32 + sl;
@@ -179,11 +183,11 @@ template <int L, bool TRANS>
 __global__ __launch_bounds__(256) void k_pack_limb(int8_t *__restrict__ dst, int64_t nkb,
                                                    const uint32_t *__restrict__ src, int64_t r0,
                                                    int64_t c0, int64_t shift, int64_t R, int64_t K,
-                                                   int logT, uint32_t p, int32_t H)
+                                                   int logT, uint32_t p, int32_t H, int neg)
 {
     __shared__ uint32_t tile[kChunk * kLdsStride];
     pack_chunk<L, TRANS>(dst, nkb, src, r0, c0, shift, R, K, logT, p, H,
-                         int64_t(blockIdx.y) * kChunk, int64_t(blockIdx.x) * kChunk, tile);
+                         int64_t(blockIdx.y) * kChunk, int64_t(blockIdx.x) * kChunk, tile, neg);
 }
 
 // Persistent form for a batch: workgroups pop runs of 64 x 64 chunks of all
@@ -220,27 +224,27 @@ __global__ __launch_bounds__(256) void k_pack_limb_batched(QueueView q, uint64_t
             if (c > c0) __syncthreads();  // the previous chunk's LDS reads are done
             if (t.trans)
                 pack_chunk<L, true>(t.dst, t.nkb, t.src, t.r0, t.c0, t.shift, t.R, t.K, t.logT, p,
-                                    H, rho0, kap0, tile);
+                                    H, rho0, kap0, tile, t.neg);
             else
                 pack_chunk<L, false>(t.dst, t.nkb, t.src, t.r0, t.c0, t.shift, t.R, t.K, t.logT, p,
-                                     H, rho0, kap0, tile);
+                                     H, rho0, kap0, tile, t.neg);
         }
     }
 }
 
 template <int L>
 hipError_t launch_limb_L(int8_t *dst, int64_t prow, int64_t nkb, const uint32_t *src, int64_t r0,
-                         int64_t c0, int64_t shift, int64_t R, int64_t K, int trans, int logT,
-                         uint32_t p, hipStream_t s)
+                         int64_t c0, int64_t shift, int64_t R, int64_t K, int trans, int neg,
+                         int logT, uint32_t p, hipStream_t s)
 {
     const int32_t H = int32_t(limb_threshold(L));
     dim3 grid(unsigned((nkb + 1) / 2), unsigned(prow / kChunk));
     if (trans)
         hipLaunchKernelGGL((k_pack_limb<L, true>), grid, dim3(256), 0, s, dst, nkb, src, r0, c0,
-                           shift, R, K, logT, p, H);
+                           shift, R, K, logT, p, H, neg);
     else
         hipLaunchKernelGGL((k_pack_limb<L, false>), grid, dim3(256), 0, s, dst, nkb, src, r0, c0,
-                           shift, R, K, logT, p, H);
+                           shift, R, K, logT, p, H, neg);
     return hipGetLastError();
 }
 
@@ -278,14 +282,14 @@ hipError_t launch_pack_limb_batched(int L, const QueueView &q, uint64_t *counter
 
 hipError_t launch_pack_limb(int8_t *dst, int64_t prow, int64_t nkb, const uint32_t *src,
                             int64_t r0, int64_t c0, int64_t shift, int64_t R, int64_t K, int trans,
-                            int logT, uint32_t p, int L, hipStream_t s)
+                            int neg, int logT, uint32_t p, int L, hipStream_t s)
 {
     if (prow <= 0 || nkb <= 0) return hipSuccess;
     switch (L) {
-    case 1: return launch_limb_L<1>(dst, prow, nkb, src, r0, c0, shift, R, K, trans, logT, p, s);
-    case 2: return launch_limb_L<2>(dst, prow, nkb, src, r0, c0, shift, R, K, trans, logT, p, s);
-    case 3: return launch_limb_L<3>(dst, prow, nkb, src, r0, c0, shift, R, K, trans, logT, p, s);
-    default: return launch_limb_L<4>(dst, prow, nkb, src, r0, c0, shift, R, K, trans, logT, p, s);
+    case 1: return launch_limb_L<1>(dst, prow, nkb, src, r0, c0, shift, R, K, trans, neg, logT, p, s);
+    case 2: return launch_limb_L<2>(dst, prow, nkb, src, r0, c0, shift, R, K, trans, neg, logT, p, s);
+    case 3: return launch_limb_L<3>(dst, prow, nkb, src, r0, c0, shift, R, K, trans, neg, logT, p, s);
+    default: return launch_limb_L<4>(dst, prow, nkb, src, r0, c0, shift, R, K, trans, neg, logT, p, s);
     }
 }
 

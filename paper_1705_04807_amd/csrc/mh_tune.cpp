@@ -163,7 +163,11 @@ int tune_batch(mh_ctx *ctx, std::vector<Plan> &plans, int L, uint32_t p, hipStre
     double best_ms = 0.0;
     for (int cfg = 0; cfg < limb_cfg_count(); ++cfg) {
         if (!cfg_fits(L, cfg)) continue;
-        for (Plan &q : plans) plan_product(q.pr, MH_MODE_LIMB_I8, q, cfg);
+        for (Plan &q : plans) {
+            const bool sub = q.sub;
+            plan_product(q.pr, MH_MODE_LIMB_I8, q, cfg);
+            q.sub = sub;
+        }
         const double ms =
             time_ms(s, [&] { return launch_batch(ctx, plans, cfg, L, p, s, scratch); }, 2);
         if (ms > 0.0 && (best < 0 || ms < best_ms)) {

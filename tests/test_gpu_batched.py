@@ -143,3 +143,29 @@ def test_batched_degenerate_and_errors(mh, ctx):
     assert mh.mh_matmul_modp_batched(ctx, d, 1, p, T, 2, 0) == mh.MH_E_BOUNDS
     assert mh.mh_matmul_modp_batched(ctx, d, 1, 1, T, 2, 0) == mh.MH_E_MODULUS
     assert mh.mh_matmul_modp_batched(ctx, d, -1, p, T, 2, 0) == mh.MH_E_INVALID
+
+
+def test_batched_subtract(mh, ctx):
+    p, T, N = 65521, 64, 1024
+    g = np.random.default_rng(4242)
+    A, B = parent_host(951, p, N), parent_host(952, p, N)
+    Cs = [parent_host(953, p, N)]
+    Ad, Bd = to_mh(mh, ctx, device_of(A), N, T), to_mh(mh, ctx, device_of(B), N, T)
+    Cds = [to_mh(mh, ctx, device_of(Cs[0]), N, T)]
+    calls = draw_batch(g, 12, N, N, N, 1, 300)
+    descs = mh.make_descs([dict(C=Cds[0].data_ptr(), A=Ad.data_ptr(), B=Bd.data_ptr(), NC=N,
+                                NA=N, NB=N, rc=c["rc"], cc=c["cc"], ra=c["ra"], ca=c["ca"],
+                                rb=c["rb"], cb=c["cb"], m=c["m"], k=c["k"], n=c["n"])
+                           for c in calls])
+    for mode in (mh.MH_MODE_LIMB_I8, mh.MH_MODE_PLAIN_U32):
+        mh.check(mh.mh_matmul_modp_batched(ctx, descs, len(calls), p, T,
+                                           mode | mh.MH_SUBTRACT, stream_handle()))
+        for c in calls:
+            oracle_sub(Cs[0], A, B, p, c)
+        assert np.array_equal(host_of(to_cart(mh, ctx, Cds[0], N, T)), Cs[0]), mode
+
+
+def oracle_sub(C, A, B, p, c):
+    import oracle
+    oracle.matmul_modp_view(C, A, B, p, c["rc"], c["cc"], c["ra"], c["ca"], c["rb"], c["cb"],
+                            c["m"], c["k"], c["n"], subtract=True)

@@ -212,3 +212,40 @@ def test_adversarial_values(mh, ctx, mode, p, kind):
     C = np.full((N, N), p - 1, np.uint32)
     P = dict(NC=N, NA=N, NB=N, rc=0, cc=0, ra=0, ca=0, rb=0, cb=0, m=N, k=N, n=N)
     run_product(mh, ctx, P, p, T, mode, C_host=C, A_host=A, B_host=B)
+
+
+@MODES
+@pytest.mark.parametrize("p", [2, 65521, P31])
+def test_subtractive_update(mh, ctx, mode, p):
+    # C := C - A.B mod p, the Schur complement step, on scattered blocks
+    N, T = 512, 64
+    A, B, C = (parent_host(s, p, N) for s in (81, 82, 83))
+    Ad, Bd, Cd = (to_mh(mh, ctx, device_of(X), N, T) for X in (A, B, C))
+    rc, cc, ra, ca, rb, cb, m, k, n = 30, 70, 100, 3, 200, 41, 300, 257, 333
+    mh.check(mh.mh_matmul_modp(ctx, Cd.data_ptr(), N, rc, cc, Ad.data_ptr(), N, ra, ca,
+                               Bd.data_ptr(), N, rb, cb, m, k, n, p, T,
+                               mode | mh.MH_SUBTRACT, stream_handle()))
+    want = C.copy()
+    oracle.matmul_modp_view(want, A, B, p, rc, cc, ra, ca, rb, cb, m, k, n, subtract=True)
+    assert np.array_equal(host_of(to_cart(mh, ctx, Cd, N, T)), want)
+    assert mh.mh_matmul_modp(ctx, Cd.data_ptr(), N, 0, 0, Ad.data_ptr(), N, 0, 0, Bd.data_ptr(),
+                             N, 0, 0, 4, 4, 4, p, T, mode | 0x200, 0) == mh.MH_E_UNSUPPORTED
+
+
+@MODES
+def test_subtractive_schur_same_parent(mh, ctx, mode):
+    # One matrix: X[rc.., cc..] -= X[ra.., ca..] X[rb.., cb..], blocks disjoint
+    N, T, p = 512, 32, P31
+    X = parent_host(91, p, N)
+    Xd = to_mh(mh, ctx, device_of(X), N, T)
+    rc, cc, ra, ca, rb, cb, m, k, n = 257, 260, 1, 2, 33, 260, 250, 190, 240
+    mh.check(mh.mh_matmul_modp(ctx, Xd.data_ptr(), N, rc, cc, Xd.data_ptr(), N, ra, ca,
+                               Xd.data_ptr(), N, rb, cb, m, k, n, p, T,
+                               mode | mh.MH_SUBTRACT, stream_handle()))
+    want = X.copy()
+    prod = np.zeros((m, n), np.uint32)
+    oracle.matmul_modp(prod, np.ascontiguousarray(X[ra:ra + m, ca:ca + k]),
+                       np.ascontiguousarray(X[rb:rb + k, cb:cb + n]), p)
+    blk = want[rc:rc + m, cc:cc + n].astype(np.int64) - prod.astype(np.int64)
+    want[rc:rc + m, cc:cc + n] = (blk % p).astype(np.uint32)
+    assert np.array_equal(host_of(to_cart(mh, ctx, Xd, N, T)), want)

@@ -114,6 +114,10 @@ def test_validation_codes():
     assert describe(p=2**31 - 1)[0] == mh.MH_OK
     assert describe(m=-1)[0] == mh.MH_E_INVALID
     assert describe(mode=7)[0] == mh.MH_E_UNSUPPORTED
+    # the subtract flag combines with every form; other high bits are refused
+    for form in (mh.MH_MODE_AUTO, mh.MH_MODE_PLAIN_U32, mh.MH_MODE_LIMB_I8):
+        assert describe(mode=form | mh.MH_SUBTRACT)[0] == mh.MH_OK
+        assert describe(mode=form | 0x200)[0] == mh.MH_E_UNSUPPORTED
 
 
 def test_limbs_and_kblock():

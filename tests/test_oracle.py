@@ -323,3 +323,22 @@ def test_limb_digits_need_enough_limbs(oracle_lib):
     # two digits represent the centred window [-32896, 32639]: 65537 > 2^16 does not fit
     _, ok = oracle.limb_digits(32640, 65537, 2)
     assert not ok
+
+
+# ---------------------------------------------------------------- subtraction
+
+@pytest.mark.parametrize("p", [2, 251, 65521, 2147483647])
+def test_subtractive_update(oracle_lib, p):
+    A, B, C = rnd(201, p, 17, 40), rnd(202, p, 40, 23), rnd(203, p, 17, 23)
+    got = C.copy()
+    oracle.matmul_modp_sub(got, A, B, p)
+    want = ((C.astype(object) - A.astype(object).dot(B.astype(object))) % p).astype(np.uint32)
+    assert np.array_equal(got, want)
+    oracle.matmul_modp(got, A, B, p)  # adding the product back restores C
+    assert np.array_equal(got, C)
+    if p == 2:  # over GF(2) subtraction is addition
+        add = C.copy()
+        oracle.matmul_modp(add, A, B, p)
+        sub = C.copy()
+        oracle.matmul_modp_sub(sub, A, B, p)
+        assert np.array_equal(add, sub)
