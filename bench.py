@@ -8,6 +8,7 @@ HBM in Morton-hybrid layout.  Prints one JSON line:
              its average duration taken from HIP events the library records
              on the stream it launches on;
   plain  = the plain uint32 kernel on the same workload (the comparator);
+  fp64   = the FP64-MFMA form on the same workload, when p < 2^26;
   cpu_baseline = the CPU oracle (triple loop, 128-bit accumulators) on a
              bounded sample of output rows of the same workload.
 
@@ -38,6 +39,8 @@ if ROOT not in sys.path:
 
 METRIC = "modular GOPS (2mnk/s) for C+=A·B mod p, MFMA/batched vs plain, bit-exact"
 INT8_PEAK_TOPS = 5000.0   # MI355X dense int8 MFMA, 5.0 POP/s
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense fp64 MFMA
+FP64_MAX_P = (1 << 26) - 1
 P31 = 2**31 - 1
 
 WORKLOADS = {
@@ -149,6 +152,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + [BATCHED])
     ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=2,
+                    help="timed steps of the FP64-MFMA form (only for p < 2^26)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -254,6 +259,31 @@ def main():
                  "gemm_ms": pg_ms / max(pg_n, 1)}
         plain["limb_speedup"] = value / plain["value"]
         log("plain: %.3f ms/step" % plain["ms_per_step"])
+
+    # ---- FP64-MFMA form (primes below 2^26 only)
+    fp64 = None
+    if args.fp64_steps > 0 and p <= FP64_MAX_P:
+        step(mh.MH_MODE_FP64)
+        stream.synchronize()
+        mh.mh_ctx_set_timing(ctx, True)
+        t0 = time.perf_counter()
+        for _ in range(args.fp64_steps):
+            step(mh.MH_MODE_FP64)
+        stream.synchronize()
+        fe = time.perf_counter() - t0
+        fg_ms, fg_n = mh.mh_ctx_kernel_time(ctx, mh.MH_K_GEMM_F64, reset=True)
+        fp_ms, fp_n = mh.mh_ctx_kernel_time(ctx, mh.MH_K_PACK, reset=True)
+        mh.mh_ctx_set_timing(ctx, False)
+        fgemm = fg_ms / max(fg_n, 1)
+        ftf = work / (fgemm * 1e-3) / 1e12
+        fp64 = {"value": work * args.fp64_steps / fe / 1e9, "unit": "GOPS",
+                "ms_per_step": fe / args.fp64_steps * 1e3, "gemm_ms": fgemm,
+                "pack_ms": fp_ms / max(fp_n, 1) if fp_n else 0.0,
+                "roofline": {"bound": "mfma", "achieved": ftf, "peak": FP64_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": ftf / FP64_PEAK_TFLOPS,
+                             "kernel": "k_gemm_f64"}}
+        fp64["limb_speedup"] = value / fp64["value"]
+        log("fp64: %.3f ms/step, gemm %.3f ms" % (fp64["ms_per_step"], fgemm))
     assert mh.mh_ctx_last_device_error(ctx) == 0
 
     cpu = None
@@ -279,6 +309,7 @@ def main():
                              "WRITE_SIZE, copy-calibrated"},
         "pack_ms": pack_ms / max(pack_n, 1),
         "plain": plain,
+        "fp64": fp64,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -75,8 +75,11 @@ enum {
 enum {
     MH_MODE_AUTO = 0,      /* pick by shape */
     MH_MODE_PLAIN_U32 = 1, /* VALU kernel, 64-bit multiply-accumulate with carry word */
-    MH_MODE_LIMB_I8 = 2    /* residues split into signed 8-bit limbs; int8 MFMA with
+    MH_MODE_LIMB_I8 = 2,   /* residues split into signed 8-bit limbs; int8 MFMA with
                               int32 accumulators; mod-p reduction once per k-block */
+    MH_MODE_FP64 = 3       /* p < 2^26 only (else MH_E_MODULUS): centred residues as
+                              doubles, FP64 MFMA, mod-p reduction deferred while every
+                              partial sum stays an integer below 2^53 in magnitude */
 };
 
 /* Or-ed into `mode`: subtractive update C := (C - A.B) mod p, the Schur
@@ -92,7 +95,8 @@ enum {
     MH_K_GEMM_PLAIN = 3,
     MH_K_GEMM_LIMB = 4,
     MH_K_BATCHED = 5,      /* one batched graph: persistent pack + persistent GEMM */
-    MH_K_COUNT = 6
+    MH_K_GEMM_F64 = 6,
+    MH_K_COUNT = 7
 };
 
 /* ---------------------------------------------------------------- context */
@@ -185,7 +189,8 @@ mh_status mh_layout_to_cartesian(mh_ctx *ctx, uint32_t *dst, int64_t ld_dst,
  * Schur update of a TU step writes one block of a matrix from two others).
  * The result is canonical (in [0,p)) and identical for every mode.
  * Errors: MH_E_INVALID, MH_E_SHAPE, MH_E_BOUNDS, MH_E_MODULUS (p outside
- * [2, 2^31-1]), MH_E_ALIAS, MH_E_UNSUPPORTED, MH_E_NOMEM.
+ * [2, 2^31-1], or p >= 2^26 with MH_MODE_FP64), MH_E_ALIAS, MH_E_UNSUPPORTED
+ * (bits of mode other than a form and MH_SUBTRACT), MH_E_NOMEM.
  */
 mh_status mh_matmul_modp(mh_ctx *ctx, uint32_t *C, int64_t NC, int64_t rc, int64_t cc,
                          const uint32_t *A, int64_t NA, int64_t ra, int64_t ca,
@@ -213,8 +218,8 @@ typedef struct {
  * between calls, through one host-to-device copy on `stream`.  Consecutive
  * batched calls of one context must be ordered (same stream or
  * synchronised), since they share the queue and the workspace.  mode:
- * MH_MODE_AUTO and MH_MODE_LIMB_I8 run the limb form; MH_MODE_PLAIN_U32 runs
- * the products one after another with the plain kernel.
+ * MH_MODE_AUTO and MH_MODE_LIMB_I8 run the limb form; MH_MODE_PLAIN_U32 and
+ * MH_MODE_FP64 run the products one after another with their own kernels.
  */
 mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *descs, int32_t count,
                                  uint32_t p, int32_t T, int32_t mode, hipStream_t stream);
@@ -235,7 +240,7 @@ typedef struct {
     int32_t in_place;       /* 1 if the plain kernel reads A and B tiles in place */
     int32_t tile_m, tile_n; /* output block of one workgroup */
     int32_t limbs;          /* limbs per residue (limb mode) */
-    int32_t kblock;         /* k-block length between reductions mod p (limb mode) */
+    int32_t kblock;         /* depth between reductions mod p (limb and FP64 forms) */
     int32_t kernel_cfg;     /* limb GEMM configuration the call would launch (-1: none) */
 } mh_plan_info;
 

@@ -37,6 +37,7 @@ MH_QUADRANT = 4
 MH_MODE_AUTO = 0
 MH_MODE_PLAIN_U32 = 1
 MH_MODE_LIMB_I8 = 2
+MH_MODE_FP64 = 3
 MH_SUBTRACT = 0x100
 
 MH_K_LAYOUT_FROM = 0
@@ -45,7 +46,8 @@ MH_K_PACK = 2
 MH_K_GEMM_PLAIN = 3
 MH_K_GEMM_LIMB = 4
 MH_K_BATCHED = 5
-MH_K_COUNT = 6
+MH_K_GEMM_F64 = 6
+MH_K_COUNT = 7
 
 # Every symbol declared in include/mh.h.
 EXPORTS = (

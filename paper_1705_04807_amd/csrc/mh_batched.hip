@@ -283,6 +283,7 @@ extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, in
     mode = form;
     if (!valid_T(T)) return MH_E_UNSUPPORTED;
     if (p < 2u || p > 0x7FFFFFFFu) return MH_E_MODULUS;
+    if (check_form_modulus(form, p) != MH_OK) return MH_E_MODULUS;
     // Validate every product first: a failing call has no effect.
     std::vector<Product> prods(count);
     for (int32_t i = 0; i < count; ++i) {
@@ -329,11 +330,12 @@ extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, in
         if (prods[i].m > 0 && prods[i].n > 0 && prods[i].k > 0) live.push_back(i);
     if (live.empty()) return MH_OK;
 
-    if (mode == MH_MODE_PLAIN_U32) {
-        // The plain form has no batched kernel: products run one after another.
+    if (mode == MH_MODE_PLAIN_U32 || mode == MH_MODE_FP64) {
+        // The plain and FP64 forms have no batched kernel: products run one
+        // after another.
         for (int32_t i : live) {
             Plan pl;
-            plan_product(prods[i], MH_MODE_PLAIN_U32, pl);
+            plan_product(prods[i], mode, pl);
             pl.sub = sub;
             mh_status s = run_plain(ctx, pl, stream);
             if (s != MH_OK) return s;

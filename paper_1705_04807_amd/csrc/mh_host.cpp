@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -377,8 +378,8 @@ void plan_product(const Product &p, int mode, Plan &pl, int forced_cfg)
         pl.tile_n = c.tile_n();
     } else {
         pl.limb_cfg = -1;
-        pl.tile_m = 64;
-        pl.tile_n = 64;
+        pl.tile_m = mode == MH_MODE_FP64 ? 128 : 64;
+        pl.tile_n = pl.tile_m;
     }
     pl.sr = p.rc % std::min<int64_t>(T, pl.tile_m);
     pl.sc = p.cc % std::min<int64_t>(T, pl.tile_n);
@@ -449,6 +450,7 @@ extern "C" mh_status mh_plan_describe(int64_t NC, int64_t rc, int64_t cc, int64_
     Product pr = make_product(nullptr, NC, rc, cc, nullptr, NA, ra, ca, nullptr, NB, rb, cb, m,
                               k, n, p, T);
     mh_status s = validate_product(pr, false);
+    if (s == MH_OK) s = check_form_modulus(form, p);
     if (s != MH_OK) return s;
     std::vector<int64_t> rcut, kcut, ccut;
     segments(m, rc, ra, T, rcut);
@@ -468,7 +470,10 @@ extern "C" mh_status mh_plan_describe(int64_t NC, int64_t rc, int64_t cc, int64_
     out->tile_m = pl.tile_m;
     out->tile_n = pl.tile_n;
     out->limbs = pl.mode == MH_MODE_LIMB_I8 ? pl.L : 0;
-    out->kblock = pl.mode == MH_MODE_LIMB_I8 ? pl.kblock : 0;
+    out->kblock = pl.mode == MH_MODE_LIMB_I8 ? pl.kblock
+                : pl.mode == MH_MODE_FP64     ? int32_t(std::min<int64_t>(
+                                                    int64_t(4) * f64_red_steps(p), INT32_MAX / 4 * 4))
+                                              : 0;
     out->kernel_cfg = pl.mode == MH_MODE_LIMB_I8 ? pl.limb_cfg : -1;
     out->gemm_tasks = (m > 0 && n > 0) ? pl.grid_m * pl.grid_n : 0;
     if (pl.mode == MH_MODE_LIMB_I8 && m > 0 && n > 0 && k > 0) {
@@ -527,6 +532,7 @@ extern "C" mh_status mh_plan_gemm_tasks(int64_t NC, int64_t rc, int64_t cc, int6
     Product pr = make_product(nullptr, NC, rc, cc, nullptr, NA, ra, ca, nullptr, NB, rb, cb, m,
                               k, n, p, T);
     mh_status s = validate_product(pr, false);
+    if (s == MH_OK) s = check_form_modulus(form, p);
     if (s != MH_OK) return s;
     *count = 0;
     if (m == 0 || n == 0) return MH_OK;
@@ -627,6 +633,8 @@ mh_status run_plain(mh_ctx *ctx, const Plan &pl, hipStream_t s)
     a.mu = barrett_mu(p.p);
     a.logT = p.logT;
     a.sub = pl.sub ? 1 : 0;
+    a.red_steps = f64_red_steps(p.p);
+    a.pinv = 1.0 / double(p.p);
     if (pl.in_place) {
         a.A = p.A;
         a.B = p.B;
@@ -661,9 +669,10 @@ mh_status run_plain(mh_ctx *ctx, const Plan &pl, hipStream_t s)
         a.a_ntc = pl.kpad / T;
         a.b_ntc = pcol / T;
     }
+    const bool f64 = pl.mode == MH_MODE_FP64;
     TimedLaunch t;
-    record_start(ctx, MH_K_GEMM_PLAIN, s, t);
-    hipError_t e = launch_gemm_plain(a, s);
+    record_start(ctx, f64 ? MH_K_GEMM_F64 : MH_K_GEMM_PLAIN, s, t);
+    hipError_t e = f64 ? launch_gemm_f64(a, s) : launch_gemm_plain(a, s);
     record_end(ctx, s, t);
     return note_error(ctx, e);
 }
@@ -729,13 +738,14 @@ extern "C" mh_status mh_matmul_modp(mh_ctx *ctx, uint32_t *C, int64_t NC, int64_
     if (!parse_mode(mode, form, sub)) return MH_E_UNSUPPORTED;
     Product pr = make_product(C, NC, rc, cc, A, NA, ra, ca, B, NB, rb, cb, m, k, n, p, T);
     mh_status s = validate_product(pr, true);
+    if (s == MH_OK) s = check_form_modulus(form, p);
     if (s != MH_OK) return s;
     if (m == 0 || n == 0 || k == 0) return MH_OK;
     Plan pl;
     plan_product(pr, form, pl);
     pl.sub = sub;
     DeviceGuard g(ctx->device);
-    if (pl.mode == MH_MODE_PLAIN_U32) return run_plain(ctx, pl, stream);
+    if (pl.mode == MH_MODE_PLAIN_U32 || pl.mode == MH_MODE_FP64) return run_plain(ctx, pl, stream);
     if (ctx->autotune) {
         int cfg = tune_get(ctx, tune_key_single(pl.L, pr));
         if (cfg < 0 && ctx->autotune == 2) cfg = tune_single(ctx, pr, stream);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -179,7 +180,7 @@ inline bool parse_mode(int32_t mode, int &form, bool &sub)
 {
     form = mode & 0xFF;
     sub = (mode & MH_SUBTRACT) != 0;
-    return (mode & ~(0xFF | MH_SUBTRACT)) == 0 && form >= MH_MODE_AUTO && form <= MH_MODE_LIMB_I8;
+    return (mode & ~(0xFF | MH_SUBTRACT)) == 0 && form >= MH_MODE_AUTO && form <= MH_MODE_FP64;
 }
 void segments(int64_t len, int64_t offA, int64_t offB, int32_t T, std::vector<int64_t> &cuts);
 
@@ -226,8 +227,26 @@ struct PlainArgs {
     uint64_t mu;         // floor((2^64 - 1) / p)
     int logT;
     int sub;             // C := C - A.B
+    int red_steps;       // FP64 form: MFMA steps (depth 4) between reductions mod p
+    double pinv;         // FP64 form: 1.0 / p rounded to nearest
 };
 hipError_t launch_gemm_plain(const PlainArgs &a, hipStream_t s);
+hipError_t launch_gemm_f64(const PlainArgs &a, hipStream_t s);
+
+// FP64 form: largest p accepted, and the MFMA steps of depth 4 between
+// reductions so that |partial sum| <= (p - 1) + 4 steps H^2 <= 2^53 with
+// H = max |centred residue|.
+constexpr uint32_t kF64MaxP = (1u << 26) - 1;
+inline int f64_red_steps(uint32_t p)
+{
+    const double H = p == 2u ? 1.0 : double((p - 1) / 2);
+    const double steps = std::floor((9007199254740992.0 - double(p)) / (4.0 * H * H));
+    return steps > double(1 << 30) ? (1 << 30) : int(steps);
+}
+inline mh_status check_form_modulus(int form, uint32_t p)
+{
+    return (form == MH_MODE_FP64 && p > kF64MaxP) ? MH_E_MODULUS : MH_OK;
+}
 
 struct LimbArgs {
     const int8_t *Ap, *Bp;

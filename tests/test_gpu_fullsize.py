@@ -1,8 +1,10 @@
 """Parity at the full benchmark sizes, in the launch configuration bench.py times.
 
-* 4096^3, p = 65521: every output against the full oracle product.
+* 4096^3, p = 65521: every output of the limb and FP64 forms against the full
+  oracle product.
 * 8192^3, p = 2^31 - 1 and the non-aligned 6000 x 3000 x 5000 product inside
-  8192^2 parents: the limb and plain forms must agree on every word; sampled
+  8192^2 parents: the limb and plain forms (and the FP64 form where p < 2^26)
+  must agree on every word; sampled
   outputs are recomputed one by one by the oracle; Freivalds' check (two
   random vectors) covers the whole block; words outside the C block are
   unchanged.
@@ -56,11 +58,15 @@ def test_4096_cube_p65521_full_oracle(mh, ctx):
     say("fullsize 4096^3")
     cart, (Am, Bm, Cm) = make_parents(mh, ctx, N, T, p, (2001, 2002, 2003))
     A, B, C0 = (host_of(X) for X in cart)
+    Cf = Cm.clone()
     run(mh, ctx, Cm, Am, Bm, N, (0,) * 6, N, N, N, p, T, mh.MH_MODE_LIMB_I8)
+    say("fullsize 4096^3 fp64")
+    run(mh, ctx, Cf, Am, Bm, N, (0,) * 6, N, N, N, p, T, mh.MH_MODE_FP64)
     got = host_of(to_cart(mh, ctx, Cm, N, T))
     want = C0.copy()
     oracle.matmul_modp(want, A, B, p)
     assert np.array_equal(got, want)
+    assert np.array_equal(host_of(to_cart(mh, ctx, Cf, N, T)), want)
 
 
 def _check_block(mh, ctx, N, T, p, off, m, k, n, seeds, samples=384):
@@ -68,13 +74,19 @@ def _check_block(mh, ctx, N, T, p, off, m, k, n, seeds, samples=384):
     torch = torch_cuda()
     cart, (Am, Bm, Cm) = make_parents(mh, ctx, N, T, p, seeds)
     Cm2 = Cm.clone()
+    Cm3 = Cm.clone() if p <= 0x3FFFFFF else None
     say("fullsize limb", N, off, m, k, n, p)
     run(mh, ctx, Cm, Am, Bm, N, off, m, k, n, p, T, mh.MH_MODE_LIMB_I8)
     say("fullsize plain", N, off, m, k, n, p)
     run(mh, ctx, Cm2, Am, Bm, N, off, m, k, n, p, T, mh.MH_MODE_PLAIN_U32)
+    if Cm3 is not None:
+        say("fullsize fp64", N, off, m, k, n, p)
+        run(mh, ctx, Cm3, Am, Bm, N, off, m, k, n, p, T, mh.MH_MODE_FP64)
     torch.cuda.synchronize()
-    # two independent kernels agree on every word of the parent
+    # independent kernels agree on every word of the parent
     assert torch.equal(Cm, Cm2)
+    if Cm3 is not None:
+        assert torch.equal(Cm, Cm3)
     got = host_of(to_cart(mh, ctx, Cm, N, T))
     A, B, C0 = (host_of(X) for X in cart)
     # outside the block nothing moved

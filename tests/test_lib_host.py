@@ -120,6 +120,30 @@ def test_validation_codes():
         assert describe(mode=form | 0x200)[0] == mh.MH_E_UNSUPPORTED
 
 
+@pytest.mark.parametrize("p", [2, 3, 251, 65521, (1 << 24) - 3, 67108859])
+def test_fp64_form_plan_and_reduction_depth(p):
+    s, info = describe(p=p, mode=mh.MH_MODE_FP64, m=200, k=150, n=100)
+    assert s == mh.MH_OK and info.mode == mh.MH_MODE_FP64
+    assert (info.tile_m, info.tile_n) == (128, 128)
+    # depth between reductions: a multiple of the MFMA depth 4 whose worst
+    # partial sum (p - 1) + depth * H^2 stays within 2^53, and the largest such
+    H = 1 if p == 2 else (p - 1) // 2
+    d = info.kblock
+    assert d % 4 == 0 and d >= 8
+    if d < 2**31 - 4:
+        assert (p - 1) + d * H * H <= 2**53
+        assert (p - 1) + (d + 4) * H * H > 2**53
+    if p == 67108859:
+        assert d == 8
+
+
+def test_fp64_form_modulus_limit():
+    assert describe(p=67108859, mode=mh.MH_MODE_FP64)[0] == mh.MH_OK
+    assert describe(p=(1 << 26) + 15, mode=mh.MH_MODE_FP64)[0] == mh.MH_E_MODULUS
+    assert describe(p=2**31 - 1, mode=mh.MH_MODE_FP64 | mh.MH_SUBTRACT)[0] == mh.MH_E_MODULUS
+    assert describe(p=2**31 - 1, mode=mh.MH_MODE_LIMB_I8)[0] == mh.MH_OK
+
+
 def test_limbs_and_kblock():
     for p, L in [(2, 1), (251, 1), (256, 1), (257, 2), (65521, 2), (65536, 2), (65537, 3),
                  ((1 << 24) - 3, 3), (2**31 - 1, 4)]:
