@@ -54,6 +54,13 @@ WORKLOADS = {
     "modp_nonaligned_8192parents_p65521_T64": dict(
         N=8192, T=64, p=65521, m=6000, k=3000, n=5000,
         off=(64, 33, 1000, 1500, 517, 2048), seeds=(3001, 3002, 3003)),
+    # the same blocks with the paper's truncation size T' = 32 and with 16
+    "modp_nonaligned_8192parents_p65521_T32": dict(
+        N=8192, T=32, p=65521, m=6000, k=3000, n=5000,
+        off=(64, 33, 1000, 1500, 517, 2048), seeds=(3001, 3002, 3003)),
+    "modp_nonaligned_8192parents_p65521_T16": dict(
+        N=8192, T=16, p=65521, m=6000, k=3000, n=5000,
+        off=(64, 33, 1000, 1500, 517, 2048), seeds=(3001, 3002, 3003)),
 }
 # 512 uneven independent products of one TU recursion level, one batched call
 BATCHED = "batched_512_tu_level_8192parents_p65521_T64"
@@ -156,6 +163,9 @@ def main():
                     help="timed steps of the FP64-MFMA form (only for p < 2^26)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--ablation", action="store_true",
+                    help="plain kernel through the planner against the elementwise comparator "
+                         "(per-element Morton-hybrid encoding, no planner) on --workload")
     ap.add_argument("--no-autotune", action="store_true",
                     help="built-in kernel configuration instead of tuning during warm-up")
     args = ap.parse_args()
@@ -203,6 +213,9 @@ def main():
                                    rb, cb, m, k, n, p, T, mode, sh), "mh_matmul_modp")
 
     work = 2.0 * m * n * k
+    if args.ablation:
+        ablation(args, mh, ctx, step, stream, work, W)
+        return
     s, info = mh.mh_plan_describe(N, rc, cc, N, ra, ca, N, rb, cb, m, k, n, p, T,
                                   mh.MH_MODE_LIMB_I8)
     mh.check(s)
@@ -313,6 +326,44 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def ablation(args, mh, ctx, step, stream, work, W):
+    """Problems P1/P2 of section 2.1 on the GPU: one kernel, two ways of reaching the
+    operands.  Prints one JSON line (not the throughput line)."""
+    import torch
+
+    def timed(mode, kernel):
+        step(mode)
+        stream.synchronize()
+        mh.mh_ctx_set_timing(ctx, True)
+        for kk in range(mh.MH_K_COUNT):
+            mh.mh_ctx_kernel_time(ctx, kk, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(mode)
+        stream.synchronize()
+        el = time.perf_counter() - t0
+        g_ms, g_n = mh.mh_ctx_kernel_time(ctx, kernel, reset=True)
+        p_ms, p_n = mh.mh_ctx_kernel_time(ctx, mh.MH_K_PACK, reset=True)
+        mh.mh_ctx_set_timing(ctx, False)
+        return {"ms_per_step": el / args.steps * 1e3, "gemm_ms": g_ms / max(g_n, 1),
+                "pack_ms": p_ms / max(p_n, 1) if p_n else 0.0,
+                "value": work * args.steps / el / 1e9, "unit": "GOPS"}
+
+    log("ablation: planner path")
+    planner = timed(mh.MH_MODE_PLAIN_U32, mh.MH_K_GEMM_PLAIN)
+    log("ablation: elementwise comparator")
+    elementwise = timed(mh.MH_MODE_PLAIN_ELEMENTWISE, mh.MH_K_GEMM_PLAIN)
+    assert mh.mh_ctx_last_device_error(ctx) == 0
+    mh.mh_ctx_destroy(ctx)
+    print(json.dumps({"ablation": "planner_vs_elementwise", "workload": args.workload,
+                      "T": W["T"], "p": W["p"], "m": W["m"], "k": W["k"], "n": W["n"],
+                      "offsets_c_a_b": list(W["off"]), "steps": args.steps,
+                      "planner": planner, "elementwise": elementwise,
+                      "planner_speedup": elementwise["ms_per_step"] / planner["ms_per_step"]}),
+          flush=True)
 
 
 def bench_batched(args):

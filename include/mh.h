@@ -77,9 +77,14 @@ enum {
     MH_MODE_PLAIN_U32 = 1, /* VALU kernel, 64-bit multiply-accumulate with carry word */
     MH_MODE_LIMB_I8 = 2,   /* residues split into signed 8-bit limbs; int8 MFMA with
                               int32 accumulators; mod-p reduction once per k-block */
-    MH_MODE_FP64 = 3       /* p < 2^26 only (else MH_E_MODULUS): centred residues as
+    MH_MODE_FP64 = 3,      /* p < 2^26 only (else MH_E_MODULUS): centred residues as
                               doubles, FP64 MFMA, mod-p reduction deferred while every
                               partial sum stays an integer below 2^53 in magnitude */
+    MH_MODE_PLAIN_ELEMENTWISE = 4 /* comparator, not a production form: the plain kernel
+                              without the planner, every element of A, B and C addressed
+                              by its own Morton-hybrid encoding where it lies (the
+                              default algorithm of section 2.2 on scattered blocks,
+                              problems P1 and P2 of section 2.1) */
 };
 
 /* Or-ed into `mode`: subtractive update C := (C - A.B) mod p, the Schur
@@ -178,6 +183,28 @@ mh_status mh_layout_to_cartesian(mh_ctx *ctx, uint32_t *dst, int64_t ld_dst,
                                  const uint32_t *src_mh, int64_t N, int32_t T,
                                  hipStream_t stream);
 
+/* Rectangular or non-power-of-two matrices (the caller side of the TU
+ * recursion, section 1, whose matrices have any shape): they are embedded in
+ * the top-left corner of the smallest Morton-hybrid parent, zero padded.
+ * mh_parent_size: *N = the smallest T * 2^q >= max(rows, cols), host only;
+ * MH_E_INVALID (rows or cols < 1, N null), MH_E_UNSUPPORTED (T, or N above
+ * 2^18). */
+mh_status mh_parent_size(int64_t rows, int64_t cols, int32_t T, int64_t *N);
+
+/* dst_mh (N*N words) <- the rows x cols Cartesian matrix src (row length
+ * ld_src >= cols) in its top-left corner, zeros elsewhere.  rows, cols <= N.
+ * Device pointers that must not overlap.  Errors as mh_layout_from_cartesian,
+ * MH_E_INVALID for rows or cols outside [1, N]. */
+mh_status mh_layout_from_cartesian_padded(mh_ctx *ctx, uint32_t *dst_mh, int64_t N,
+                                          const uint32_t *src, int64_t ld_src, int64_t rows,
+                                          int64_t cols, int32_t T, hipStream_t stream);
+
+/* The rows x cols top-left corner of src_mh (N*N words) -> dst (row length
+ * ld_dst >= cols); words of dst outside rows x cols are not written. */
+mh_status mh_layout_to_cartesian_padded(mh_ctx *ctx, uint32_t *dst, int64_t ld_dst,
+                                        int64_t rows, int64_t cols, const uint32_t *src_mh,
+                                        int64_t N, int32_t T, hipStream_t stream);
+
 /* --------------------------------------------------------------- product */
 
 /*
@@ -218,8 +245,8 @@ typedef struct {
  * between calls, through one host-to-device copy on `stream`.  Consecutive
  * batched calls of one context must be ordered (same stream or
  * synchronised), since they share the queue and the workspace.  mode:
- * MH_MODE_AUTO and MH_MODE_LIMB_I8 run the limb form; MH_MODE_PLAIN_U32 and
- * MH_MODE_FP64 run the products one after another with their own kernels.
+ * MH_MODE_AUTO and MH_MODE_LIMB_I8 run the limb form; the other forms run the
+ * products one after another with their own kernels.
  */
 mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *descs, int32_t count,
                                  uint32_t p, int32_t T, int32_t mode, hipStream_t stream);

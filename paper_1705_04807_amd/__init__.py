@@ -38,6 +38,7 @@ MH_MODE_AUTO = 0
 MH_MODE_PLAIN_U32 = 1
 MH_MODE_LIMB_I8 = 2
 MH_MODE_FP64 = 3
+MH_MODE_PLAIN_ELEMENTWISE = 4
 MH_SUBTRACT = 0x100
 
 MH_K_LAYOUT_FROM = 0
@@ -56,7 +57,8 @@ EXPORTS = (
     "mh_classify_submatrix", "mh_layout_from_cartesian", "mh_layout_to_cartesian",
     "mh_matmul_modp", "mh_matmul_modp_batched", "mh_plan_describe", "mh_plan_leaves",
     "mh_plan_gemm_tasks", "mh_ctx_set_autotune", "mh_ctx_tune_lookup", "mh_ctx_tune_cache_save",
-    "mh_ctx_tune_cache_load",
+    "mh_ctx_tune_cache_load", "mh_parent_size", "mh_layout_from_cartesian_padded",
+    "mh_layout_to_cartesian_padded",
 )
 
 
@@ -113,6 +115,9 @@ def _load():
         "mh_classify_submatrix": ([I64, I32, I64, I64, I64, I64, ct.POINTER(U32)], ct.c_int),
         "mh_layout_from_cartesian": ([P, P, P, I64, I64, I32, P], ct.c_int),
         "mh_layout_to_cartesian": ([P, P, I64, P, I64, I32, P], ct.c_int),
+        "mh_parent_size": ([I64, I64, I32, ct.POINTER(I64)], ct.c_int),
+        "mh_layout_from_cartesian_padded": ([P, P, I64, P, I64, I64, I64, I32, P], ct.c_int),
+        "mh_layout_to_cartesian_padded": ([P, P, I64, I64, I64, P, I64, I32, P], ct.c_int),
         "mh_matmul_modp": ([P, P, I64, I64, I64, P, I64, I64, I64, P, I64, I64, I64, I64, I64,
                             I64, U32, I32, I32, P], ct.c_int),
         "mh_matmul_modp_batched": ([P, ct.POINTER(mh_mm_desc), I32, U32, I32, I32, P], ct.c_int),
@@ -218,6 +223,23 @@ def mh_layout_from_cartesian(ctx, dst_mh: int, src: int, ld_src: int, N: int, T:
 def mh_layout_to_cartesian(ctx, dst: int, ld_dst: int, src_mh: int, N: int, T: int,
                            stream: int = 0) -> int:
     return lib.mh_layout_to_cartesian(ctx, dst, ld_dst, src_mh, N, T, stream)
+
+
+def mh_parent_size(rows: int, cols: int, T: int):
+    """Returns (status, N)."""
+    n = ct.c_int64(0)
+    s = lib.mh_parent_size(rows, cols, T, ct.byref(n))
+    return s, n.value
+
+
+def mh_layout_from_cartesian_padded(ctx, dst_mh: int, N: int, src: int, ld_src: int, rows: int,
+                                    cols: int, T: int, stream: int = 0) -> int:
+    return lib.mh_layout_from_cartesian_padded(ctx, dst_mh, N, src, ld_src, rows, cols, T, stream)
+
+
+def mh_layout_to_cartesian_padded(ctx, dst: int, ld_dst: int, rows: int, cols: int, src_mh: int,
+                                  N: int, T: int, stream: int = 0) -> int:
+    return lib.mh_layout_to_cartesian_padded(ctx, dst, ld_dst, rows, cols, src_mh, N, T, stream)
 
 
 def mh_matmul_modp(ctx, C: int, NC: int, rc: int, cc: int, A: int, NA: int, ra: int, ca: int,

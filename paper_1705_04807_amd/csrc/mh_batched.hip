@@ -330,9 +330,9 @@ extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, in
         if (prods[i].m > 0 && prods[i].n > 0 && prods[i].k > 0) live.push_back(i);
     if (live.empty()) return MH_OK;
 
-    if (mode == MH_MODE_PLAIN_U32 || mode == MH_MODE_FP64) {
-        // The plain and FP64 forms have no batched kernel: products run one
-        // after another.
+    if (mode != MH_MODE_AUTO && mode != MH_MODE_LIMB_I8) {
+        // The plain, FP64 and elementwise forms have no batched kernel:
+        // products run one after another.
         for (int32_t i : live) {
             Plan pl;
             plan_product(prods[i], mode, pl);

@@ -36,6 +36,17 @@ __device__ __forceinline__ uint32_t mod_u64(uint64_t x, uint32_t p, uint64_t mu)
     return uint32_t(r);
 }
 
+// x mod (2^31 - 1) for any 64-bit x: since 2^31 = 1 mod p, x = hi 2^31 + lo
+// folds to hi + lo.  Two folds leave a value below 2^31 + 2^4, one
+// conditional subtraction finishes.
+__device__ __forceinline__ uint32_t mod_m31(uint64_t x)
+{
+    constexpr uint64_t M = 0x7FFFFFFFull;
+    x = (x & M) + (x >> 31);
+    x = (x & M) + (x >> 31);
+    return uint32_t(x >= M ? x - M : x);
+}
+
 // Largest i in [lo, n) with prefix[i] <= t, given prefix[lo] <= t < prefix[n]
 // (prefix non-decreasing).  A workgroup's popped work indices only grow, so
 // it searches forward from its previous answer: a galloping search costs

@@ -4,7 +4,8 @@
 // v_mad_u64_u32 (32x32 -> 64-bit multiply-add, carry out to a lane mask)
 // and a 32-bit carry count updated with v_addc.  Products are below 2^62,
 // so no reduction mod p is needed inside the k-loop; the accumulator is
-// reduced once per output (Barrett) and added to C.
+// reduced once per output (Barrett, or shift-and-add folding for the
+// Mersenne prime 2^31 - 1) and added to C.
 //
 // A workgroup computes a 64 x 64 output block aligned to C's tile grid, so
 // its writes stay inside whole C tiles (contained pieces, section 2.1).
@@ -41,21 +42,38 @@ __device__ __forceinline__ void mac4(uint64_t (&lo)[4], uint32_t (&hi)[4], uint3
         : "v"(a), "v"(b[0]), "v"(b[1]), "v"(b[2]), "v"(b[3]));
 }
 
-// Address of view element (r, c): in-place Morton-hybrid parent whose view
-// starts at tile (tr0, tc0), or a tile-major panel with ntc tile columns.
-__device__ __forceinline__ uint64_t view_addr(int mhview, int64_t tr0, int64_t tc0, int64_t ntc,
-                                              int64_t r, int64_t c, int logT)
+// Operand views (one kernel instance each):
+enum View {
+    kPanel = 0,        // tile-major panel with ntc tile columns
+    kInPlace = 1,      // Morton-hybrid parent, view starting at tile (tr0, tc0)
+    kElementwise = 2,  // Morton-hybrid parent, view starting at element (tr0, tc0),
+                       // every element addressed by its own encoding
+};
+
+// Address of view element (r, c).  Parents have at most 2^18 rows and
+// T >= 16, so tile coordinates stay below 2^14 (32-bit dilation) and tile
+// indices below 2^28.
+template <int VIEW>
+__device__ __forceinline__ uint64_t view_addr(int64_t tr0, int64_t tc0, int64_t ntc, int64_t r,
+                                              int64_t c, int logT)
 {
-    const uint64_t m = (1u << logT) - 1;
-    const uint64_t inner = (uint64_t(r) & m) << logT | (uint64_t(c) & m);
-    uint64_t tile;
-    if (mhview)
-        tile = tile_z(uint64_t(tr0 + (r >> logT)), uint64_t(tc0 + (c >> logT)));
-    else
-        tile = uint64_t(r >> logT) * uint64_t(ntc) + uint64_t(c >> logT);
-    return (tile << (2 * logT)) | inner;
+    if (VIEW == kElementwise) return mh_offset(uint64_t(tr0 + r), uint64_t(tc0 + c), logT);
+    const uint32_t m = (1u << logT) - 1;
+    const uint32_t inner = (uint32_t(r) & m) << logT | (uint32_t(c) & m);
+    const uint32_t tr = uint32_t(r) >> logT, tc = uint32_t(c) >> logT;
+    const uint32_t tile = VIEW == kInPlace
+                              ? (spread16(uint32_t(tr0) + tr) << 1) | spread16(uint32_t(tc0) + tc)
+                              : tr * uint32_t(ntc) + tc;
+    return (uint64_t(tile) << (2 * logT)) | inner;
 }
 
+// kElementwise is the comparator for the locality argument of section 2.1
+// (problems P1 and P2): the same arithmetic with the planner taken out.  The
+// output blocks follow the product's own coordinates instead of C's tile
+// grid, and A, B and C are read and written where they lie, each element
+// through a full Morton-hybrid encoding, so a block that straddles tiles is
+// traversed across them.
+template <int VIEW>
 __global__ __launch_bounds__(256) void k_gemm_plain(PlainArgs a)
 {
     __shared__ uint32_t As[BK * kAStride];  // As[kk][row]
@@ -86,7 +104,7 @@ __global__ __launch_bounds__(256) void k_gemm_plain(PlainArgs a)
                 const int64_t rho = rho0 + rr;
                 uint32_t v = 0;
                 if (kok && rho >= a.sr && rho < a.sr + a.m)
-                    v = a.A[view_addr(a.a_mh, a.a_tr0, a.a_tc0, a.a_ntc, rho, kap, a.logT)];
+                    v = a.A[view_addr<VIEW>(a.a_tr0, a.a_tc0, a.a_ntc, rho, kap, a.logT)];
                 As[kk * kAStride + rr] = v;
             }
         }
@@ -101,7 +119,7 @@ __global__ __launch_bounds__(256) void k_gemm_plain(PlainArgs a)
                 const int64_t kap = kap0 + kk;
                 uint32_t v = 0;
                 if (cok && kap >= klo && kap < khi)
-                    v = a.B[view_addr(a.b_mh, a.b_tr0, a.b_tc0, a.b_ntc, kap, gam, a.logT)];
+                    v = a.B[view_addr<VIEW>(a.b_tr0, a.b_tc0, a.b_ntc, kap, gam, a.logT)];
                 Bs[kk * BN + cc] = v;
             }
         }
@@ -122,6 +140,9 @@ __global__ __launch_bounds__(256) void k_gemm_plain(PlainArgs a)
     // 2^64 mod p, for folding the carry word
     uint32_t r64 = mod_u64(~uint64_t(0), a.p, a.mu) + 1;
     if (r64 == a.p) r64 = 0;
+    // p = 2^31 - 1 (the prime of the large-prime workloads): 2^64 = 4 mod p
+    // and shifts and adds replace the Barrett products.
+    const bool mersenne = a.p == 0x7FFFFFFFu;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int64_t rho = rho0 + ty * 4 + i;
@@ -130,8 +151,13 @@ __global__ __launch_bounds__(256) void k_gemm_plain(PlainArgs a)
         for (int j = 0; j < 4; ++j) {
             const int64_t gam = gam0 + tx * 4 + j;
             if (gam < a.sc || gam >= a.sc + a.n) continue;
-            const uint64_t hpart = uint64_t(mod_u64(hi[i][j], a.p, a.mu)) * r64;
-            const uint32_t r = mod_u64(uint64_t(mod_u64(lo[i][j], a.p, a.mu)) + hpart, a.p, a.mu);
+            uint32_t r;
+            if (mersenne) {
+                r = mod_m31(uint64_t(mod_m31(lo[i][j])) + (uint64_t(hi[i][j]) << 2));
+            } else {
+                const uint64_t hpart = uint64_t(mod_u64(hi[i][j], a.p, a.mu)) * r64;
+                r = mod_u64(uint64_t(mod_u64(lo[i][j], a.p, a.mu)) + hpart, a.p, a.mu);
+            }
             const uint64_t off = mh_offset(uint64_t(a.row0C + rho), uint64_t(a.col0C + gam), a.logT);
             const uint32_t add = a.sub ? (r ? a.p - r : 0u) : r;  // C - r = C + (p - r)
             uint32_t c = a.C[off] + add;
@@ -147,7 +173,19 @@ hipError_t launch_gemm_plain(const PlainArgs &a, hipStream_t s)
 {
     const int64_t groups = a.grid_m * a.grid_n;
     if (groups <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gemm_plain, dim3(unsigned(groups)), dim3(256), 0, s, a);
+    // A and B are both panels, both in place, or both elementwise.
+    if (a.a_mh != a.b_mh) return hipErrorInvalidValue;
+    switch (a.a_mh) {
+    case kPanel:
+        hipLaunchKernelGGL(k_gemm_plain<kPanel>, dim3(unsigned(groups)), dim3(256), 0, s, a);
+        break;
+    case kInPlace:
+        hipLaunchKernelGGL(k_gemm_plain<kInPlace>, dim3(unsigned(groups)), dim3(256), 0, s, a);
+        break;
+    default:
+        hipLaunchKernelGGL(k_gemm_plain<kElementwise>, dim3(unsigned(groups)), dim3(256), 0, s,
+                           a);
+    }
     return hipGetLastError();
 }
 

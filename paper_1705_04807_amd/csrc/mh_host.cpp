@@ -381,8 +381,10 @@ void plan_product(const Product &p, int mode, Plan &pl, int forced_cfg)
         pl.tile_m = mode == MH_MODE_FP64 ? 128 : 64;
         pl.tile_n = pl.tile_m;
     }
-    pl.sr = p.rc % std::min<int64_t>(T, pl.tile_m);
-    pl.sc = p.cc % std::min<int64_t>(T, pl.tile_n);
+    // The elementwise comparator works in the product's own coordinates.
+    const bool ew = mode == MH_MODE_PLAIN_ELEMENTWISE;
+    pl.sr = ew ? 0 : p.rc % std::min<int64_t>(T, pl.tile_m);
+    pl.sc = ew ? 0 : p.cc % std::min<int64_t>(T, pl.tile_n);
     pl.row0C = p.rc - pl.sr;
     pl.col0C = p.cc - pl.sc;
     pl.prow = (pl.sr + p.m + pl.tile_m - 1) / pl.tile_m * pl.tile_m;
@@ -393,6 +395,10 @@ void plan_product(const Product &p, int mode, Plan &pl, int forced_cfg)
         pl.sk = 0;
         pl.kpad = (p.k + 63) / 64 * 64;  // an even number of 32-deep k-blocks
         pl.in_place = false;
+    } else if (ew) {
+        pl.sk = 0;
+        pl.kpad = p.k;
+        pl.in_place = true;
     } else {
         // In place when A's tile rows line up with the panel rows, B's tile
         // columns with the panel columns, and A's tile columns with B's tile rows.
@@ -561,42 +567,75 @@ extern "C" mh_status mh_plan_gemm_tasks(int64_t NC, int64_t rc, int64_t cc, int6
 
 // ================================================================ layout
 
+// Shared by the square and the padded conversions: dst/src are checked for
+// overlap over the bytes each side really touches.
+static mh_status layout_common(mh_ctx *ctx, bool to_mh, uint32_t *mhbuf, uint32_t *cart,
+                               int64_t ld, int64_t rows, int64_t cols, int64_t N, int32_t T,
+                               hipStream_t stream)
+{
+    if (!ctx || !mhbuf || !cart) return MH_E_INVALID;
+    mh_status s = check_parent(N, T);
+    if (s != MH_OK) return s;
+    if (rows < 1 || cols < 1 || rows > N || cols > N || ld < cols) return MH_E_INVALID;
+    uintptr_t m0 = (uintptr_t)mhbuf, m1 = m0 + 4 * (uintptr_t)(N * N);
+    uintptr_t c0 = (uintptr_t)cart, c1 = c0 + 4 * (uintptr_t)((rows - 1) * ld + cols);
+    if (m0 < c1 && c0 < m1) return MH_E_ALIAS;
+    DeviceGuard g(ctx->device);
+    TimedLaunch t;
+    record_start(ctx, to_mh ? MH_K_LAYOUT_FROM : MH_K_LAYOUT_TO, stream, t);
+    hipError_t e = to_mh ? launch_layout_from(mhbuf, cart, ld, rows, cols, N, log2i(T), stream)
+                         : launch_layout_to(cart, ld, rows, cols, mhbuf, N, log2i(T), stream);
+    record_end(ctx, stream, t);
+    return note_error(ctx, e);
+}
+
 extern "C" mh_status mh_layout_from_cartesian(mh_ctx *ctx, uint32_t *dst_mh, const uint32_t *src,
                                               int64_t ld_src, int64_t N, int32_t T,
                                               hipStream_t stream)
 {
-    if (!ctx || !dst_mh || !src) return MH_E_INVALID;
-    mh_status s = check_parent(N, T);
-    if (s != MH_OK) return s;
     if (ld_src < N) return MH_E_INVALID;
-    uintptr_t d0 = (uintptr_t)dst_mh, d1 = d0 + 4 * (uintptr_t)(N * N);
-    uintptr_t s0 = (uintptr_t)src, s1 = s0 + 4 * (uintptr_t)((N - 1) * ld_src + N);
-    if (d0 < s1 && s0 < d1) return MH_E_ALIAS;
-    DeviceGuard g(ctx->device);
-    TimedLaunch t;
-    record_start(ctx, MH_K_LAYOUT_FROM, stream, t);
-    hipError_t e = launch_layout_from(dst_mh, src, ld_src, N, log2i(T), stream);
-    record_end(ctx, stream, t);
-    return note_error(ctx, e);
+    return layout_common(ctx, true, dst_mh, const_cast<uint32_t *>(src), ld_src, N, N, N, T,
+                         stream);
 }
 
 extern "C" mh_status mh_layout_to_cartesian(mh_ctx *ctx, uint32_t *dst, int64_t ld_dst,
                                             const uint32_t *src_mh, int64_t N, int32_t T,
                                             hipStream_t stream)
 {
-    if (!ctx || !dst || !src_mh) return MH_E_INVALID;
-    mh_status s = check_parent(N, T);
-    if (s != MH_OK) return s;
     if (ld_dst < N) return MH_E_INVALID;
-    uintptr_t s0 = (uintptr_t)src_mh, s1 = s0 + 4 * (uintptr_t)(N * N);
-    uintptr_t d0 = (uintptr_t)dst, d1 = d0 + 4 * (uintptr_t)((N - 1) * ld_dst + N);
-    if (d0 < s1 && s0 < d1) return MH_E_ALIAS;
-    DeviceGuard g(ctx->device);
-    TimedLaunch t;
-    record_start(ctx, MH_K_LAYOUT_TO, stream, t);
-    hipError_t e = launch_layout_to(dst, ld_dst, src_mh, N, log2i(T), stream);
-    record_end(ctx, stream, t);
-    return note_error(ctx, e);
+    return layout_common(ctx, false, const_cast<uint32_t *>(src_mh), dst, ld_dst, N, N, N, T,
+                         stream);
+}
+
+extern "C" mh_status mh_parent_size(int64_t rows, int64_t cols, int32_t T, int64_t *N)
+{
+    if (!N || rows < 1 || cols < 1) return MH_E_INVALID;
+    if (!valid_T(T)) return MH_E_UNSUPPORTED;
+    int64_t n = T;
+    while (n < rows || n < cols) {
+        if (n >= kMaxN) return MH_E_UNSUPPORTED;
+        n *= 2;
+    }
+    *N = n;
+    return MH_OK;
+}
+
+extern "C" mh_status mh_layout_from_cartesian_padded(mh_ctx *ctx, uint32_t *dst_mh, int64_t N,
+                                                     const uint32_t *src, int64_t ld_src,
+                                                     int64_t rows, int64_t cols, int32_t T,
+                                                     hipStream_t stream)
+{
+    return layout_common(ctx, true, dst_mh, const_cast<uint32_t *>(src), ld_src, rows, cols, N,
+                         T, stream);
+}
+
+extern "C" mh_status mh_layout_to_cartesian_padded(mh_ctx *ctx, uint32_t *dst, int64_t ld_dst,
+                                                   int64_t rows, int64_t cols,
+                                                   const uint32_t *src_mh, int64_t N, int32_t T,
+                                                   hipStream_t stream)
+{
+    return layout_common(ctx, false, const_cast<uint32_t *>(src_mh), dst, ld_dst, rows, cols, N,
+                         T, stream);
 }
 
 // ================================================================ product
@@ -635,7 +674,15 @@ mh_status run_plain(mh_ctx *ctx, const Plan &pl, hipStream_t s)
     a.sub = pl.sub ? 1 : 0;
     a.red_steps = f64_red_steps(p.p);
     a.pinv = 1.0 / double(p.p);
-    if (pl.in_place) {
+    if (pl.mode == MH_MODE_PLAIN_ELEMENTWISE) {
+        a.A = p.A;
+        a.B = p.B;
+        a.a_mh = a.b_mh = 2;
+        a.a_tr0 = p.ra;  // element origins
+        a.a_tc0 = p.ca;
+        a.b_tr0 = p.rb;
+        a.b_tc0 = p.cb;
+    } else if (pl.in_place) {
         a.A = p.A;
         a.B = p.B;
         a.a_mh = a.b_mh = 1;
@@ -745,7 +792,7 @@ extern "C" mh_status mh_matmul_modp(mh_ctx *ctx, uint32_t *C, int64_t NC, int64_
     plan_product(pr, form, pl);
     pl.sub = sub;
     DeviceGuard g(ctx->device);
-    if (pl.mode == MH_MODE_PLAIN_U32 || pl.mode == MH_MODE_FP64) return run_plain(ctx, pl, stream);
+    if (pl.mode != MH_MODE_LIMB_I8) return run_plain(ctx, pl, stream);
     if (ctx->autotune) {
         int cfg = tune_get(ctx, tune_key_single(pl.L, pr));
         if (cfg < 0 && ctx->autotune == 2) cfg = tune_single(ctx, pr, stream);

@@ -180,7 +180,7 @@ inline bool parse_mode(int32_t mode, int &form, bool &sub)
 {
     form = mode & 0xFF;
     sub = (mode & MH_SUBTRACT) != 0;
-    return (mode & ~(0xFF | MH_SUBTRACT)) == 0 && form >= MH_MODE_AUTO && form <= MH_MODE_FP64;
+    return (mode & ~(0xFF | MH_SUBTRACT)) == 0 && form >= MH_MODE_AUTO && form <= MH_MODE_PLAIN_ELEMENTWISE;
 }
 void segments(int64_t len, int64_t offA, int64_t offB, int32_t T, std::vector<int64_t> &cuts);
 
@@ -192,10 +192,11 @@ int limb_cfg_default(int L, int64_t m, int64_t n, int64_t k);
 // ------------------------------------------------------ kernel launchers
 // All return hipSuccess or the launch error; they do not synchronise.
 
-hipError_t launch_layout_from(uint32_t *dst, const uint32_t *src, int64_t ld, int64_t N,
-                              int logT, hipStream_t s);
-hipError_t launch_layout_to(uint32_t *dst, int64_t ld, const uint32_t *src, int64_t N,
-                            int logT, hipStream_t s);
+// rows x cols Cartesian words <-> N x N Morton-hybrid parent (zero padded).
+hipError_t launch_layout_from(uint32_t *dst, const uint32_t *src, int64_t ld, int64_t rows,
+                              int64_t cols, int64_t N, int logT, hipStream_t s);
+hipError_t launch_layout_to(uint32_t *dst, int64_t ld, int64_t rows, int64_t cols,
+                            const uint32_t *src, int64_t N, int logT, hipStream_t s);
 
 // u32 tile panel for the plain kernel: view rows x cols of T x T tiles,
 // tile-major.  Source element of panel (r, c): trans ? (o0 + c, i0 + r)
@@ -216,7 +217,7 @@ struct PlainArgs {
     const uint32_t *A;   // MH parent (in place) or tile-major panel
     const uint32_t *B;
     uint32_t *C;
-    int a_mh, b_mh;      // 1: MH parent; 0: panel
+    int a_mh, b_mh;      // 1: MH parent; 0: panel; 2: MH parent, view at any element
     int64_t a_tr0, a_tc0, a_ntc;  // A view origin in tiles (MH) / tile columns (panel)
     int64_t b_tr0, b_tc0, b_ntc;
     int64_t sr, sc, sk;  // valid panel rows [sr, sr+m), cols [sc, sc+n), depth [sk, sk+k)

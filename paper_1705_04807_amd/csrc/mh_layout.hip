@@ -20,10 +20,15 @@ __host__ __device__ constexpr int tiles_per_group(int logT)
     return (2 * logT >= 12) ? 1 : (1 << (12 - 2 * logT));
 }
 
+// Cartesian side: rows x cols words (row length ld); the Morton-hybrid
+// parent is padded beyond them: TO_MH writes zeros there, the other way
+// leaves the Cartesian words outside rows x cols untouched.  VEC moves four
+// words at once and requires cols to be a multiple of four.
 template <bool TO_MH, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_layout(uint32_t *__restrict__ dst,
                                                      const uint32_t *__restrict__ src,
-                                                     int64_t ld, int logT, uint64_t ntiles)
+                                                     int64_t ld, int64_t rows, int64_t cols,
+                                                     int logT, uint64_t ntiles)
 {
     const int T = 1 << logT;
     const int tpg = tiles_per_group(logT);
@@ -37,55 +42,59 @@ __global__ __launch_bounds__(kThreads) void k_layout(uint32_t *__restrict__ dst,
         const int r = (e >> logT) & (T - 1);
         const int c = e & (T - 1);
         const uint64_t I = compact32(tz >> 1), J = compact32(tz);
-        const uint64_t cart = ((I << logT) + r) * uint64_t(ld) + (J << logT) + c;
+        const int64_t gi = int64_t(I << logT) + r, gj = int64_t(J << logT) + c;
+        const bool inside = gi < rows && gj < cols;  // whole group when VEC
+        const uint64_t cart = uint64_t(gi) * uint64_t(ld) + uint64_t(gj);
         const uint64_t mh = (tz << (2 * logT)) + (uint64_t(r) << logT) + c;
         if (VEC) {
             if (TO_MH) {
-                uint4 v = *reinterpret_cast<const uint4 *>(src + cart);
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (inside) v = *reinterpret_cast<const uint4 *>(src + cart);
                 *reinterpret_cast<uint4 *>(dst + mh) = v;
-            } else {
+            } else if (inside) {
                 uint4 v = *reinterpret_cast<const uint4 *>(src + mh);
                 *reinterpret_cast<uint4 *>(dst + cart) = v;
             }
         } else {
             if (TO_MH)
-                dst[mh] = src[cart];
-            else
+                dst[mh] = inside ? src[cart] : 0u;
+            else if (inside)
                 dst[cart] = src[mh];
         }
     }
 }
 
 template <bool TO_MH>
-hipError_t launch(uint32_t *dst, const uint32_t *src, int64_t ld, int64_t N, int logT,
-                  hipStream_t s)
+hipError_t launch(uint32_t *dst, const uint32_t *src, int64_t ld, int64_t rows, int64_t cols,
+                  int64_t N, int logT, hipStream_t s)
 {
     const uint64_t q = uint64_t(N) >> logT;
     const uint64_t ntiles = q * q;
     const int tpg = tiles_per_group(logT);
     const uint64_t groups = (ntiles + tpg - 1) / tpg;
-    const bool vec = (ld % 4 == 0) && ((uintptr_t)src % 16 == 0) && ((uintptr_t)dst % 16 == 0);
+    const bool vec = (ld % 4 == 0) && (cols % 4 == 0) && ((uintptr_t)src % 16 == 0) &&
+                     ((uintptr_t)dst % 16 == 0);
     if (vec)
         hipLaunchKernelGGL((k_layout<TO_MH, true>), dim3(unsigned(groups)), dim3(kThreads), 0, s,
-                           dst, src, ld, logT, ntiles);
+                           dst, src, ld, rows, cols, logT, ntiles);
     else
         hipLaunchKernelGGL((k_layout<TO_MH, false>), dim3(unsigned(groups)), dim3(kThreads), 0, s,
-                           dst, src, ld, logT, ntiles);
+                           dst, src, ld, rows, cols, logT, ntiles);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_layout_from(uint32_t *dst, const uint32_t *src, int64_t ld, int64_t N, int logT,
-                              hipStream_t s)
+hipError_t launch_layout_from(uint32_t *dst, const uint32_t *src, int64_t ld, int64_t rows,
+                              int64_t cols, int64_t N, int logT, hipStream_t s)
 {
-    return launch<true>(dst, src, ld, N, logT, s);
+    return launch<true>(dst, src, ld, rows, cols, N, logT, s);
 }
 
-hipError_t launch_layout_to(uint32_t *dst, int64_t ld, const uint32_t *src, int64_t N, int logT,
-                            hipStream_t s)
+hipError_t launch_layout_to(uint32_t *dst, int64_t ld, int64_t rows, int64_t cols,
+                            const uint32_t *src, int64_t N, int logT, hipStream_t s)
 {
-    return launch<false>(dst, src, ld, N, logT, s);
+    return launch<false>(dst, src, ld, rows, cols, N, logT, s);
 }
 
 }  // namespace mh

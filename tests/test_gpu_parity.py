@@ -98,7 +98,7 @@ def run_product(mh, ctx, P, p, T, mode, seeds=(1, 2, 3), C_host=None, A_host=Non
     assert mh.mh_ctx_last_device_error(ctx) == 0
 
 
-MODES = pytest.mark.parametrize("mode", [1, 2])
+MODES = pytest.mark.parametrize("mode", [1, 2, 4])  # plain, limb, elementwise comparator
 
 
 @MODES
@@ -249,3 +249,57 @@ def test_subtractive_schur_same_parent(mh, ctx, mode):
     blk = want[rc:rc + m, cc:cc + n].astype(np.int64) - prod.astype(np.int64)
     want[rc:rc + m, cc:cc + n] = (blk % p).astype(np.uint32)
     assert np.array_equal(host_of(to_cart(mh, ctx, Xd, N, T)), want)
+
+
+# ------------------------------------------------------- padded parents
+
+@pytest.mark.parametrize("rows,cols,T,ldpad", [(1000, 700, 32, 0), (333, 517, 16, 3),
+                                               (64, 64, 64, 0), (129, 1, 128, 5)])
+def test_padded_layout_roundtrip(mh, ctx, rows, cols, T, ldpad):
+    torch = torch_cuda()
+    s, N = mh.mh_parent_size(rows, cols, T)
+    mh.check(s)
+    say("padded layout", rows, cols, T, N)
+    X = parent_host(301 + T, P31, max(rows, cols))[:rows, :cols]
+    ld = cols + ldpad
+    Xp = np.full((rows, ld), 0xDEADBEEF, np.uint32)
+    Xp[:, :cols] = X
+    src = device_of(Xp)
+    dst = torch.full((N * N,), -1, dtype=torch.int32, device="cuda")
+    mh.check(mh.mh_layout_from_cartesian_padded(ctx, dst.data_ptr(), N, src.data_ptr(), ld,
+                                                rows, cols, T, stream_handle()))
+    full = np.zeros((N, N), np.uint32)
+    full[:rows, :cols] = X
+    assert np.array_equal(host_of(dst), oracle.mh_from_cartesian(full, T))
+    back = device_of(np.full((rows, ld), 7, np.uint32))
+    mh.check(mh.mh_layout_to_cartesian_padded(ctx, back.data_ptr(), ld, rows, cols,
+                                              dst.data_ptr(), N, T, stream_handle()))
+    got = host_of(back)
+    assert np.array_equal(got[:, :cols], X)
+    assert (got[:, cols:] == 7).all()  # row padding of the destination untouched
+    assert mh.mh_layout_from_cartesian_padded(ctx, dst.data_ptr(), N, src.data_ptr(), ld,
+                                              N + 1, cols, T, 0) == mh.MH_E_INVALID
+
+
+@MODES
+def test_schur_update_on_padded_matrix(mh, ctx, mode):
+    # The caller side of a TU step on a 1000 x 1000 matrix (not a power of two):
+    # pad into a 1024 x 1024 parent, X22 -= X21 X12 mod p, read the matrix back.
+    torch = torch_cuda()
+    p, T, n0, h = 65521, 32, 1000, 437
+    s, N = mh.mh_parent_size(n0, n0, T)
+    X = parent_host(401, p, n0)
+    src = device_of(X)
+    Xm = torch.empty(N * N, dtype=torch.int32, device="cuda")
+    mh.check(mh.mh_layout_from_cartesian_padded(ctx, Xm.data_ptr(), N, src.data_ptr(), n0, n0,
+                                                n0, T, stream_handle()))
+    r = n0 - h
+    mh.check(mh.mh_matmul_modp(ctx, Xm.data_ptr(), N, h, h, Xm.data_ptr(), N, h, 0,
+                               Xm.data_ptr(), N, 0, h, r, h, r, p, T, mode | mh.MH_SUBTRACT,
+                               stream_handle()))
+    out = device_of(np.zeros((n0, n0), np.uint32))
+    mh.check(mh.mh_layout_to_cartesian_padded(ctx, out.data_ptr(), n0, n0, n0, Xm.data_ptr(), N,
+                                              T, stream_handle()))
+    want = X.copy()
+    oracle.matmul_modp_view(want, X, X, p, h, h, h, 0, 0, h, r, h, r, subtract=True)
+    assert np.array_equal(host_of(out), want)

@@ -137,6 +137,25 @@ def test_fp64_form_plan_and_reduction_depth(p):
         assert d == 8
 
 
+def test_parent_size():
+    for rows, cols, T, N in [(6000, 5000, 64, 8192), (64, 64, 64, 64), (65, 1, 64, 128),
+                             (1, 1, 16, 16), (1000, 1000, 32, 1024), (1, 129, 128, 256),
+                             (2**18, 7, 128, 2**18)]:
+        assert mh.mh_parent_size(rows, cols, T) == (mh.MH_OK, N), (rows, cols, T)
+    assert mh.mh_parent_size(0, 5, 64)[0] == mh.MH_E_INVALID
+    assert mh.mh_parent_size(5, 5, 8)[0] == mh.MH_E_UNSUPPORTED
+    assert mh.mh_parent_size(2**18 + 1, 5, 64)[0] == mh.MH_E_UNSUPPORTED
+
+
+def test_elementwise_comparator_plan():
+    # no planner: output blocks in the product's own coordinates, no packing
+    s, info = describe(mode=mh.MH_MODE_PLAIN_ELEMENTWISE, rc=3, cc=5, ra=7, ca=9, rb=11, cb=13,
+                       m=130, k=70, n=65)
+    assert s == mh.MH_OK and info.mode == mh.MH_MODE_PLAIN_ELEMENTWISE
+    assert (info.tile_m, info.tile_n) == (64, 64)
+    assert info.gemm_tasks == 3 * 2 and info.pack_chunks == 0
+
+
 def test_fp64_form_modulus_limit():
     assert describe(p=67108859, mode=mh.MH_MODE_FP64)[0] == mh.MH_OK
     assert describe(p=(1 << 26) + 15, mode=mh.MH_MODE_FP64)[0] == mh.MH_E_MODULUS
