@@ -100,7 +100,8 @@ __device__ __forceinline__ void pack_chunk(int8_t *__restrict__ dst, int64_t nkb
 
     // The chunk's source rectangle is read as aligned 16-byte groups: a
     // window of 17 groups (68 words) along the contiguous source direction
-    // covers the 64 needed words whatever their alignment.  An aligned group
+    // covers the 64 needed words whatever their alignment (16 groups when
+    // the window starts on a group boundary).  An aligned group
     // never crosses a tile row (T is a multiple of 4), so each group is one
     // contained piece; groups wholly outside the block are not read (they may
     // lie beyond the parent), and words outside it are stored as zero.
@@ -132,7 +133,8 @@ __device__ __forceinline__ void pack_chunk(int8_t *__restrict__ dst, int64_t nkb
                 ok = kap < K;
                 srow = r0 + kap;
             }
-            ok = ok && gcol + 4 > clo && gcol < chi;
+            // the 17th group is needed only when the window starts inside a group
+            ok = ok && gcol + 4 > clo && gcol < chi && (mis != 0 || g < G - 1);
             uint4 v = make_uint4(0, 0, 0, 0);
             if (ok)
                 v = *reinterpret_cast<const uint4 *>(
