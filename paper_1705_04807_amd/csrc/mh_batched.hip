@@ -38,7 +38,7 @@ int batch_cfg(int L, const std::vector<Plan> &plans)
     int cfg = (L <= 2 || area <= 512.0 * 512.0) ? 6 : 4;
     if (const char *e = std::getenv("MH_LIMB_CFG")) {  // explicit override (tuning runs)
         int c = std::atoi(e);
-        if (c >= 0 && c < limb_cfg_count() && (2 * L - 1) * limb_cfg(c).wm * limb_cfg(c).wn <= 14)
+        if (limb_cfg_fits(L, c))
             cfg = c;
     }
     return cfg;

@@ -29,7 +29,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 // One workgroup's output block (gm, gn) of the product described by `a`.
-template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS>
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF>
 __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t gn)
 {
     constexpr int S = 2 * L - 1;
@@ -172,10 +172,14 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
         // reads its fragments back with conflict-free 16-byte LDS reads, and
         // every A or B block crosses the L2 once per workgroup instead of
         // once per wave that uses it.
-        extern __shared__ v4i lds_buf[];  // [2][NBLK][64]
+        extern __shared__ v4i lds_buf[];  // [NBUF][NBLK][64]
         constexpr int NW = WAVES_M * WAVES_N;
         constexpr int NA = WM * WAVES_M * KS * L;
         constexpr int NBLK = (WM * WAVES_M + WN * WAVES_N) * KS * L;
+        constexpr int R = (NBLK + NW - 1) / NW;  // 16-byte loads per wave and stage (at most)
+        // With more than two buffers, the wait below counts this wave's loads
+        // of the later stages, so every wave must issue the same number.
+        static_assert(NBUF == 2 || (NBLK % NW == 0 && (NBUF - 2) * R < 64), "vmcnt count");
         const int wv = __builtin_amdgcn_readfirstlane(wave);
         const int64_t slabA0 = gm * (WM * WAVES_M), slabB0 = gn * (WN * WAVES_N);
         // Block addresses are wave-uniform (scalar registers); only the lane's
@@ -185,30 +189,46 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
         const uint32_t lane_off = uint32_t(lane) * 16u;
         auto issue = [&](int64_t st, int buf) {
             const int64_t kb = st * KS;
-            static_for<(NBLK + NW - 1) / NW>([&](auto r) {
+            static_for<R>([&](auto r) {
                 const int b = wv + NW * r;
-                if (b < NBLK) {
+                if (NBLK % NW == 0 || b < NBLK) {
                     const bool isb = b >= NA;
                     const int bb = isb ? b - NA : b;
                     const int sl = bb / (KS * L), q = (bb / L) % KS, t = bb % L;
                     const int64_t slab = (isb ? slabB0 : slabA0) + sl;
-                    const char *blk = (isb ? gb : ga) + (((slab * nkb + kb + q) * L + t) << 10);
+                    const char *blk =
+                        (isb ? gb : ga) + (((slab * nkb + kb + q) * L + t) << 10);
                     __builtin_amdgcn_global_load_lds(
                         blk + lane_off,
-                        (__attribute__((address_space(3))) void *)(lds_buf + (buf * NBLK + b) * 64),
+                        (__attribute__((address_space(3))) void *)(lds_buf +
+                                                                    (buf * NBLK + b) * 64),
                         16, 0, 0);
                 }
             });
         };
+        // s_waitcnt vmcnt(n) with expcnt and lgkmcnt left free
+        constexpr int kWaitInFlight = ((NBUF - 2) * R & 15) | (7 << 4) | (15 << 8) |
+                                      (((NBUF - 2) * R >> 4) << 14);
         const int64_t nst = nkb / KS, st_red = a.kb_per_red / KS;
-        issue(0, 0);
+        // NBUF - 1 stages in flight ahead of the one being multiplied
+        static_for<NBUF - 1>([&](auto s0) {
+            if (int64_t(s0) < nst) issue(int64_t(s0), int(s0));
+        });
         for (int64_t st0 = 0; st0 < nst; st0 += st_red) {
             const int64_t st1 = (st0 + st_red < nst) ? st0 + st_red : nst;
             for (int64_t st = st0; st < st1; ++st) {
-                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's blocks of stage st landed
-                __syncthreads();                     // every wave's did; buffer (st+1)&1 is free again
-                if (st + 1 < nst) issue(st + 1, int((st + 1) & 1));
-                const v4i *sb = lds_buf + (st & 1) * (NBLK * 64) + lane;
+                // This wave's blocks of stage st landed.  Loads complete in
+                // order, so it suffices that at most the NBUF - 2 later stages
+                // are outstanding; the last stages, and the first stage after
+                // an epilogue (whose C accesses were issued after the
+                // prefetches), wait for everything.
+                if (NBUF > 2 && st + NBUF - 2 < nst && !(st == st0 && st0 > 0))
+                    __builtin_amdgcn_s_waitcnt(kWaitInFlight);
+                else
+                    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+                __syncthreads();  // every wave's did; buffer (st - 1) mod NBUF is free again
+                if (st + NBUF - 1 < nst) issue(st + NBUF - 1, int((st + NBUF - 1) % NBUF));
+                const v4i *sb = lds_buf + (st % NBUF) * (NBLK * 64) + lane;
                 static_for<KS>([&](auto q) {
                     v4i fa[WM][L], fb[WN][L];
                     static_for<WM>([&](auto i) {
@@ -238,12 +258,12 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
     }
 }
 
-template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS>
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb(LimbArgs a)
 {
     int64_t gm, gn;
     tile_of(blockIdx.x, a.grid_m, a.grid_n, 8, gm, gn);
-    gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS>(a, gm, gn);
+    gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>(a, gm, gn);
 }
 
 // Persistent form for a batch of products: every workgroup pops output
@@ -251,7 +271,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb(LimbArgs a
 // exit test is the same for all waves of the group).  Blocks are numbered
 // call by call in the queue's order (largest k first); a forward search over
 // the per-call prefix sums finds the call of a block.
-template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS>
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb_batched(QueueView q,
                                                                               uint64_t *counter)
 {
@@ -268,24 +288,25 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb_batched(Qu
         lo = find_from(q.tile_prefix, ncalls, lo, t);
         const LimbArgs a = q.calls[lo];
         const int64_t local = t - q.tile_prefix[lo];
-        gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS>(a, local / a.grid_n, local % a.grid_n);
+        gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>(a, local / a.grid_n,
+                                                             local % a.grid_n);
     }
 }
 
-template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS>
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF>
 constexpr size_t lds_bytes()
 {
-    return LDS ? size_t(2) * (WM * WAVES_M + WN * WAVES_N) * KS * L * 1024 : 0;
+    return LDS ? size_t(NBUF) * (WM * WAVES_M + WN * WAVES_N) * KS * L * 1024 : 0;
 }
 
-template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS>
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF = 2>
 hipError_t launch_one(const LimbArgs &a, hipStream_t s)
 {
     const int64_t groups = a.grid_m * a.grid_n;
     if (groups <= 0) return hipSuccess;
     if (a.nkb % KS || a.kb_per_red % KS) return hipErrorInvalidValue;
-    auto kern = k_gemm_limb<L, WM, WN, WAVES_M, WAVES_N, KS, LDS>;
-    const size_t shm = lds_bytes<L, WM, WN, WAVES_M, WAVES_N, KS, LDS>();
+    auto kern = k_gemm_limb<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>;
+    const size_t shm = lds_bytes<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>();
     if (shm > 65536) {
         static bool set = false;
         if (!set && hipFuncSetAttribute((const void *)kern,
@@ -298,9 +319,11 @@ hipError_t launch_one(const LimbArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-// Configuration table: {id, WM, WN, waves_m, waves_n, KS, LDS}.  (2L-1) * WM * WN
-// accumulator tiles of 16 registers must fit beside the fragments: at most
-// 14 tiles.
+// Configuration table: {id, WM, WN, waves_m, waves_n, KS, LDS, NBUF, LMAX}.
+// (2L-1) * WM * WN accumulator tiles of 16 registers must fit beside the
+// fragments: at most 14 tiles.  NBUF: LDS stage buffers (NBUF - 1 stages in
+// flight while one is multiplied).  LMAX: largest limb count the
+// configuration is built for (LDS capacity).
 const LimbKernelCfg kCfgs[] = {
     {0, 1, 2, 2, 2, 1, 0},  // 64 x 128
     {1, 1, 1, 2, 2, 1, 0},  // 64 x 64
@@ -313,15 +336,23 @@ const LimbKernelCfg kCfgs[] = {
     {8, 2, 2, 2, 2, 2, 1},   // 128 x 128, LDS-shared stages (L <= 2)
     {9, 1, 1, 2, 2, 2, 1},   // 64 x 64, LDS-shared stages
     {10, 2, 1, 2, 2, 2, 1},  // 128 x 64, LDS-shared stages
+    {11, 1, 1, 2, 4, 2, 1},        // 64 x 128, 8 waves of 32 x 32, LDS-shared stages
+    {12, 1, 1, 4, 2, 2, 1},        // 128 x 64, 8 waves of 32 x 32, LDS-shared stages
+    {13, 1, 1, 4, 4, 2, 1, 2, 2},  // 128 x 128, 16 waves of 32 x 32, LDS-shared stages (L <= 2)
+    {14, 1, 1, 4, 4, 2, 1, 3, 2},  // the same, two stages in flight (L <= 2)
+    {15, 1, 2, 4, 2, 2, 1, 2, 2},  // 128 x 128, 8 waves of 32 x 64, LDS-shared stages (L <= 2)
 };
 
-bool cfg_fits(int L, const LimbKernelCfg &c) { return (2 * L - 1) * c.wm * c.wn <= 14; }
+bool cfg_fits(int L, const LimbKernelCfg &c)
+{
+    return (2 * L - 1) * c.wm * c.wn <= 14 && L <= c.lmax;
+}
 
-template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS>
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF = 2>
 hipError_t launch_batched_one(const QueueView &q, uint64_t *counter, int num_cu, hipStream_t s)
 {
-    auto kern = k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS>;
-    const size_t shm = lds_bytes<L, WM, WN, WAVES_M, WAVES_N, KS, LDS>();
+    auto kern = k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>;
+    const size_t shm = lds_bytes<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>();
     if (shm > 65536) {
         static bool set = false;
         if (!set && hipFuncSetAttribute((const void *)kern,
@@ -361,6 +392,18 @@ hipError_t dispatch_batched_L(int cfg, const QueueView &q, uint64_t *counter, in
         return hipErrorInvalidValue;
     case 9: return launch_batched_one<L, 1, 1, 2, 2, 2, true>(q, counter, num_cu, s);
     case 10: return launch_batched_one<L, 2, 1, 2, 2, 2, true>(q, counter, num_cu, s);
+    case 11: return launch_batched_one<L, 1, 1, 2, 4, 2, true>(q, counter, num_cu, s);
+    case 12: return launch_batched_one<L, 1, 1, 4, 2, 2, true>(q, counter, num_cu, s);
+    case 13:
+        if constexpr (L <= 2) return launch_batched_one<L, 1, 1, 4, 4, 2, true>(q, counter, num_cu, s);
+        return hipErrorInvalidValue;
+    case 14:
+        if constexpr (L <= 2)
+            return launch_batched_one<L, 1, 1, 4, 4, 2, true, 3>(q, counter, num_cu, s);
+        return hipErrorInvalidValue;
+    case 15:
+        if constexpr (L <= 2) return launch_batched_one<L, 1, 2, 4, 2, 2, true>(q, counter, num_cu, s);
+        return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
 }
@@ -386,6 +429,17 @@ hipError_t dispatch_L(int cfg, const LimbArgs &a, hipStream_t s)
         return hipErrorInvalidValue;
     case 9: return launch_one<L, 1, 1, 2, 2, 2, true>(a, s);
     case 10: return launch_one<L, 2, 1, 2, 2, 2, true>(a, s);
+    case 11: return launch_one<L, 1, 1, 2, 4, 2, true>(a, s);
+    case 12: return launch_one<L, 1, 1, 4, 2, 2, true>(a, s);
+    case 13:
+        if constexpr (L <= 2) return launch_one<L, 1, 1, 4, 4, 2, true>(a, s);
+        return hipErrorInvalidValue;
+    case 14:
+        if constexpr (L <= 2) return launch_one<L, 1, 1, 4, 4, 2, true, 3>(a, s);
+        return hipErrorInvalidValue;
+    case 15:
+        if constexpr (L <= 2) return launch_one<L, 1, 2, 4, 2, 2, true>(a, s);
+        return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
 }
@@ -394,13 +448,17 @@ hipError_t dispatch_L(int cfg, const LimbArgs &a, hipStream_t s)
 
 int limb_cfg_count() { return int(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 const LimbKernelCfg &limb_cfg(int idx) { return kCfgs[idx]; }
+bool limb_cfg_fits(int L, int idx)
+{
+    return idx >= 0 && idx < limb_cfg_count() && cfg_fits(L, kCfgs[idx]);
+}
 
 int limb_cfg_default(int L, int64_t m, int64_t n, int64_t k)
 {
     (void)k;
     if (m * n <= int64_t(512) * 512) return 6;  // 64 x 64 output blocks
-    if (L <= 2) return 5;                      // 128 x 128
-    return 4;                                  // 64 x 128
+    if (L <= 2) return 11;                     // 64 x 128, 8 waves sharing LDS stages
+    return 4;                                  // 64 x 128, register-pipelined
 }
 
 hipError_t launch_gemm_limb_batched(int cfg, int L, const QueueView &q, uint64_t *counter,

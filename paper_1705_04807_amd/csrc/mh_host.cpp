@@ -365,11 +365,17 @@ void plan_product(const Product &p, int mode, Plan &pl, int forced_cfg)
     pl.mode = mode;
     pl.L = limbs_for(p.p);
     pl.kblock = kblock_for(pl.L);
+    if (const char *e = std::getenv("MH_LIMB_KBLOCK")) {
+        // shorter k-blocks than the bound allows (always exact; used by tests
+        // to run the epilogue between k-blocks at small sizes)
+        const int v = std::atoi(e);
+        if (v >= 64 && v % 64 == 0 && v < pl.kblock) pl.kblock = v;
+    }
     if (mode == MH_MODE_LIMB_I8) {
         pl.limb_cfg = limb_cfg_default(pl.L, p.m, p.n, p.k);
         if (const char *e = std::getenv("MH_LIMB_CFG")) {  // explicit override (tuning runs)
             int c = std::atoi(e);
-            if (c >= 0 && c < limb_cfg_count() && (2 * pl.L - 1) * limb_cfg(c).wm * limb_cfg(c).wn <= 14)
+            if (limb_cfg_fits(pl.L, c))
                 pl.limb_cfg = c;
         }
         if (forced_cfg >= 0) pl.limb_cfg = forced_cfg;

@@ -135,6 +135,8 @@ struct LimbKernelCfg {
     int waves_m, waves_n;
     int ks;              // 32-deep k-blocks per pipeline stage
     int lds;             // 1: stages shared through LDS by the workgroup's waves
+    int nbuf = 2;        // stage buffers (LDS, or register sets)
+    int lmax = 4;        // largest limb count built for this configuration
     int tile_m() const { return 32 * wm * waves_m; }
     int tile_n() const { return 32 * wn * waves_n; }
 };
@@ -187,6 +189,7 @@ void segments(int64_t len, int64_t offA, int64_t offB, int32_t T, std::vector<in
 // limb kernel table
 int limb_cfg_count();
 const LimbKernelCfg &limb_cfg(int idx);
+bool limb_cfg_fits(int L, int idx);  // accumulators fit and the instance is built for L
 int limb_cfg_default(int L, int64_t m, int64_t n, int64_t k);
 
 // ------------------------------------------------------ kernel launchers

@@ -45,11 +45,6 @@ std::string device_tag(mh_ctx *ctx)
     return buf;
 }
 
-bool cfg_fits(int L, int cfg)
-{
-    const LimbKernelCfg &c = limb_cfg(cfg);
-    return (2 * L - 1) * c.wm * c.wn <= 14;
-}
 
 // Scratch output parent for tuning runs (the caller's C is never written).
 uint32_t *tune_scratch(mh_ctx *ctx, int64_t N)
@@ -135,7 +130,7 @@ int tune_single(mh_ctx *ctx, const Product &p, hipStream_t s)
     int best = -1;
     double best_ms = 0.0;
     for (int cfg = 0; cfg < limb_cfg_count(); ++cfg) {
-        if (!cfg_fits(L, cfg)) continue;
+        if (!limb_cfg_fits(L, cfg)) continue;
         Plan pl;
         plan_product(q, MH_MODE_LIMB_I8, pl, cfg);
         const double ms = time_ms(s, [&] { return run_limb(ctx, pl, s); }, 2);
@@ -162,7 +157,7 @@ int tune_batch(mh_ctx *ctx, std::vector<Plan> &plans, int L, uint32_t p, hipStre
     int best = -1;
     double best_ms = 0.0;
     for (int cfg = 0; cfg < limb_cfg_count(); ++cfg) {
-        if (!cfg_fits(L, cfg)) continue;
+        if (!limb_cfg_fits(L, cfg)) continue;
         for (Plan &q : plans) {
             const bool sub = q.sub;
             plan_product(q.pr, MH_MODE_LIMB_I8, q, cfg);
