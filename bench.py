@@ -40,6 +40,9 @@ if ROOT not in sys.path:
 METRIC = "modular GOPS (2mnk/s) for C+=A·B mod p, MFMA/batched vs plain, bit-exact"
 INT8_PEAK_TOPS = 5000.0   # MI355X dense int8 MFMA, 5.0 POP/s
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense fp64 MFMA
+# Plain kernel: one multiply-accumulate = v_mad_u64_u32 + v_addc_co_u32, two
+# full-rate VALU instructions; 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz / 2.
+PLAIN_PEAK_TMACS = 256 * 4 * 16 * 2.4e9 / 2 / 1e12
 FP64_MAX_P = (1 << 26) - 1
 P31 = 2**31 - 1
 
@@ -148,8 +151,19 @@ def cpu_baseline(A_dev, B_dev, W, budget_s=12.0):
     rows = max(probe, (rows // nt) * nt) if rows >= nt else rows
     t = run(rows) if rows != probe else t
     gops = 2.0 * rows * n * k / t / 1e9
-    return {"value": gops, "unit": "GOPS", "cores": nt, "kind": "oracle",
+    return {"value": gops, "unit": "GOPS", "cores": nt, "kind": "oracle", "cpu": cpu_model(),
             "sample": "%d of %d output rows (all %d columns, k=%d), %.1f s" % (rows, m, n, k, t)}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
@@ -267,9 +281,13 @@ def main():
         pg_ms, pg_n = mh.mh_ctx_kernel_time(ctx, mh.MH_K_GEMM_PLAIN, reset=True)
         mh.mh_ctx_kernel_time(ctx, mh.MH_K_PACK, reset=True)
         mh.mh_ctx_set_timing(ctx, False)
+        pgemm = pg_ms / max(pg_n, 1)
+        tmacs = work / 2 / (pgemm * 1e-3) / 1e12
         plain = {"value": work * args.plain_steps / pe / 1e9, "unit": "GOPS",
-                 "ms_per_step": pe / args.plain_steps * 1e3,
-                 "gemm_ms": pg_ms / max(pg_n, 1)}
+                 "ms_per_step": pe / args.plain_steps * 1e3, "gemm_ms": pgemm,
+                 "roofline": {"bound": "alu", "achieved": tmacs, "peak": PLAIN_PEAK_TMACS,
+                              "unit": "T multiply-accumulates/s",
+                              "frac": tmacs / PLAIN_PEAK_TMACS, "kernel": "k_gemm_plain"}}
         plain["limb_speedup"] = value / plain["value"]
         log("plain: %.3f ms/step" % plain["ms_per_step"])
 
