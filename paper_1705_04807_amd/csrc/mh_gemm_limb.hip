@@ -71,15 +71,22 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
             return r;
         };
         double r[WM][WN][16];
+        // Three shifts (L = 2) need one reduction: 65536 T_2 + 256 T_1 + T_0
+        // is below 2^48 in magnitude as well.
+        constexpr int S0 = S == 3 ? 3 : 1;  // shifts taken by the first reduction
         static_for<WM>([&](auto i) {
             static_for<WN>([&](auto j) {
                 static_for<16>([&](auto v) {
-                    r[i][j][v] = red(double(acc[S - 1][i][j][int(v)]));
+                    double x = double(acc[S - 1][i][j][int(v)]);
+                    if constexpr (S0 == 3)
+                        x = fma(x, 65536.0, fma(double(acc[1][i][j][int(v)]), 256.0,
+                                                double(acc[0][i][j][int(v)])));
+                    r[i][j][v] = red(x);
                 });
-                acc[S - 1][i][j] = v16i{0};
+                static_for<S0>([&](auto t) { acc[S - 1 - t][i][j] = v16i{0}; });
             });
         });
-        static_for<(S - 1) / 2>([&](auto q) {
+        static_for<(S - S0) / 2>([&](auto q) {
             constexpr int hi = S - 2 - 2 * q, lo = hi - 1;
             static_for<WM>([&](auto i) {
                 static_for<WN>([&](auto j) {
@@ -94,16 +101,24 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
                 });
             });
         });
+        // Word offsets in C with 32-bit dilation (parents have at most 2^18
+        // rows and T >= 16, so tile coordinates stay below 2^14); the column
+        // part is the lane's, the row part changes per output.
+        const uint32_t tmask = (1u << a.logT) - 1;
         static_for<WM>([&](auto i) {
             static_for<WN>([&](auto j) {
                 const int64_t gam = gn * BN + (wni * WN + j) * 32 + (lane & 31);
                 if (gam < a.sc || gam >= a.sc + a.n) return;
-                const uint64_t ccol = uint64_t(a.col0C + gam);
+                const uint32_t colC = uint32_t(a.col0C + gam);
+                const uint32_t colbits = spread16(colC >> a.logT), colin = colC & tmask;
                 static_for<16>([&](auto v) {
                     const int row = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
                     const int64_t rho = gm * BM + (wmi * WM + i) * 32 + row;
                     if (rho < a.sr || rho >= a.sr + a.m) return;
-                    const uint64_t off = mh_offset(uint64_t(a.row0C + rho), ccol, a.logT);
+                    const uint32_t rowC = uint32_t(a.row0C + rho);
+                    const uint32_t tile = (spread16(rowC >> a.logT) << 1) | colbits;
+                    const uint64_t off = (uint64_t(tile) << (2 * a.logT)) |
+                                         ((rowC & tmask) << a.logT) | colin;
                     uint32_t c = a.C[off] + uint32_t(r[i][j][v]);
                     if (c >= a.p) c -= a.p;
                     a.C[off] = c;
@@ -167,8 +182,8 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
     } else {
         // The workgroup's blocks of one stage (all A slabs, then all B slabs,
         // KS k-blocks x L limbs each) go global -> LDS with one 16-byte
-        // global_load_lds per lane and block, spread over the waves; LDS is
-        // double-buffered by stage.  Blocks land in lane order, so each wave
+        // global_load_lds per lane and block, spread over the waves; LDS holds
+        // NBUF stages.  Blocks land in lane order, so each wave
         // reads its fragments back with conflict-free 16-byte LDS reads, and
         // every A or B block crosses the L2 once per workgroup instead of
         // once per wave that uses it.
