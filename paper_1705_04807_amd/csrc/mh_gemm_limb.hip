@@ -102,10 +102,16 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
             });
         });
         // Word offsets in C with 32-bit dilation (parents have at most 2^18
-        // rows and T >= 16, so tile coordinates stay below 2^14); the column
-        // part is the lane's, the row part changes per output.
+        // rows and T >= 16, so tile coordinates stay below 2^14).  The column
+        // part is the lane's.  A 32-row block starts on a multiple of
+        // min(T, 32) in C (the panel shift), so its rows 0-15 and 16-31 each
+        // lie in one tile row: two dilations per block serve its 16 outputs.
         const uint32_t tmask = (1u << a.logT) - 1;
         static_for<WM>([&](auto i) {
+            const int64_t rho0 = gm * BM + (wmi * WM + i) * 32;  // first panel row of the block
+            const uint32_t rowC0 = uint32_t(a.row0C + rho0);
+            const uint32_t rowbits[2] = {spread16(rowC0 >> a.logT) << 1,
+                                         spread16((rowC0 + 16) >> a.logT) << 1};
             static_for<WN>([&](auto j) {
                 const int64_t gam = gn * BN + (wni * WN + j) * 32 + (lane & 31);
                 if (gam < a.sc || gam >= a.sc + a.n) return;
@@ -113,10 +119,10 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
                 const uint32_t colbits = spread16(colC >> a.logT), colin = colC & tmask;
                 static_for<16>([&](auto v) {
                     const int row = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-                    const int64_t rho = gm * BM + (wmi * WM + i) * 32 + row;
+                    const int64_t rho = rho0 + row;
                     if (rho < a.sr || rho >= a.sr + a.m) return;
-                    const uint32_t rowC = uint32_t(a.row0C + rho);
-                    const uint32_t tile = (spread16(rowC >> a.logT) << 1) | colbits;
+                    const uint32_t rowC = rowC0 + uint32_t(row);
+                    const uint32_t tile = rowbits[v >= 8 ? 1 : 0] | colbits;
                     const uint64_t off = (uint64_t(tile) << (2 * a.logT)) |
                                          ((rowC & tmask) << a.logT) | colin;
                     uint32_t c = a.C[off] + uint32_t(r[i][j][v]);
