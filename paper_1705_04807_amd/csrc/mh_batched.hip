@@ -4,7 +4,8 @@
 // The calls of one recursion level of a TU factorisation are independent
 // (section 2.2, Prop. 2.6: the recursive calls can be cast in parallel), so
 // a whole batch runs as
-//   reset counters -> persistent pack kernel -> persistent GEMM kernel
+//   reset counters -> persistent pack kernels (A, then B panels) ->
+//   persistent GEMM kernel
 // on one stream.  Each persistent kernel has a fixed grid (CUs x occupancy)
 // and pops work items through an atomic counter until the queue is empty,
 // so the graph's topology never changes: a new batch only rewrites the
@@ -26,7 +27,7 @@ namespace {
 
 __global__ void k_reset_counters(uint64_t *c)
 {
-    if (threadIdx.x < 2) c[threadIdx.x] = 0;
+    if (threadIdx.x < kBatchCounters) c[threadIdx.x] = 0;
 }
 
 int batch_cfg(int L, const std::vector<Plan> &plans)
@@ -71,7 +72,8 @@ mh_status ensure_queue(mh_ctx *ctx, int64_t ncalls)
         (void)hipGetLastError();
         return MH_E_NOMEM;
     }
-    if (!b.counters && hipMalloc((void **)&b.counters, 2 * sizeof(uint64_t)) != hipSuccess) {
+    if (!b.counters &&
+        hipMalloc((void **)&b.counters, kBatchCounters * sizeof(uint64_t)) != hipSuccess) {
         b.counters = nullptr;
         (void)hipGetLastError();
         return MH_E_NOMEM;
@@ -107,7 +109,7 @@ mh_status ensure_graph(mh_ctx *ctx, int cfg, int L)
         return MH_E_DEVICE;
     hipError_t e1 = launch_reset_counters(b.counters, cs);
     hipError_t e2 = launch_pack_limb_batched(L, q, b.counters, ctx->num_cu, cs);
-    hipError_t e3 = launch_gemm_limb_batched(cfg, L, q, b.counters + 1, ctx->num_cu, cs);
+    hipError_t e3 = launch_gemm_limb_batched(cfg, L, q, b.counters + 2, ctx->num_cu, cs);
     hipGraph_t g = nullptr;
     hipError_t e4 = hipStreamEndCapture(cs, &g);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || !g) {
@@ -212,15 +214,11 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
         const int64_t nkb = pl.kpad / 32;
         int8_t *Ap = (int8_t *)(ws + aoff[order[q]]);
         int8_t *Bp = (int8_t *)(ws + boff[order[q]]);
-        PackTask &ta = hq.packs[2 * q];
-        PackTask &tb = hq.packs[2 * q + 1];
-        ta = PackTask{pr.A, Ap, pr.ra, pr.ca, pl.sr, pr.m, pr.k, pl.prow, nkb, 0, pr.logT, 0, 0};
-        tb = PackTask{pr.B, Bp, pr.rb, pr.cb, pl.sc, pr.n, pr.k, pl.pcol, nkb, 1, pr.logT,
-                      pl.sub ? 1 : 0, 0};
-        hq.pack_prefix[2 * q] = pack_total;
-        pack_total += (pl.prow / 64) * ((nkb + 1) / 2);
-        hq.pack_prefix[2 * q + 1] = pack_total;
-        pack_total += (pl.pcol / 64) * ((nkb + 1) / 2);
+        // A panels are tasks [0, ncalls), B panels [ncalls, 2 ncalls)
+        hq.packs[q] =
+            PackTask{pr.A, Ap, pr.ra, pr.ca, pl.sr, pr.m, pr.k, pl.prow, nkb, 0, pr.logT, 0, 0};
+        hq.packs[ncalls + q] = PackTask{pr.B, Bp, pr.rb, pr.cb, pl.sc, pr.n, pr.k, pl.pcol, nkb,
+                                        1, pr.logT, pl.sub ? 1 : 0, 0};
         LimbArgs &a = hq.calls[q];
         std::memset(&a, 0, sizeof(a));
         a.Ap = Ap;
@@ -243,6 +241,11 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
         a.logT = pr.logT;
         hq.tile_prefix[q] = tile_total;
         tile_total += pl.grid_m * pl.grid_n;
+    }
+    for (int64_t t = 0; t < 2 * ncalls; ++t) {
+        const PackTask &pt = hq.packs[t];
+        hq.pack_prefix[t] = pack_total;
+        pack_total += (pt.prow / 64) * ((pt.nkb + 1) / 2);
     }
     hq.pack_prefix[2 * ncalls] = pack_total;
     hq.tile_prefix[ncalls] = tile_total;

@@ -323,7 +323,9 @@ inline QueueView queue_view(void *base, int64_t cap)
     return q;
 }
 
-hipError_t launch_pack_limb_batched(int L, const QueueView &q, uint64_t *counter, int num_cu,
+// Work counters of one batched graph: A packing, B packing, GEMM.
+constexpr int kBatchCounters = 3;
+hipError_t launch_pack_limb_batched(int L, const QueueView &q, uint64_t *counters, int num_cu,
                                     hipStream_t s);
 hipError_t launch_gemm_limb_batched(int cfg, int L, const QueueView &q, uint64_t *counter,
                                     int num_cu, hipStream_t s);

@@ -193,29 +193,35 @@ __global__ __launch_bounds__(256) void k_pack_limb(int8_t *__restrict__ dst, int
 }
 
 // Persistent form for a batch: workgroups pop runs of 64 x 64 chunks of all
-// the operand panels of the batch through an atomic counter; a forward search
-// over the per-operand prefix sums finds the operand of a run's first chunk,
-// and the following chunks step forward from it.  Barriers between chunks
-// (and after reading the popped index) order the reuse of the LDS tile.
-template <int L>
+// the A panels (TRANS = false: tasks [0, ncalls)) or the B panels (TRANS =
+// true: tasks [ncalls, 2 ncalls)) of the batch through an atomic counter; a
+// forward search over the per-operand prefix sums finds the operand of a
+// run's first chunk, and the following chunks step forward from it.
+// Barriers between chunks (and after reading the popped index) order the
+// reuse of the LDS tile.  One instance per direction keeps the register
+// count, and so the number of resident workgroups, of the single-operand
+// kernel.
+template <int L, bool TRANS>
 __global__ __launch_bounds__(256) void k_pack_limb_batched(QueueView q, uint64_t *counter)
 {
     constexpr int64_t kGrab = 8;  // chunks per pop: one atomic and one search per 8 chunks
     __shared__ uint32_t tile[kChunk * kLdsStride];
     __shared__ int64_t chunk_s;
-    const int64_t total = q.hdr->pack_chunks;
-    const int64_t npack = q.hdr->npack;
+    const int64_t ncalls = q.hdr->ncalls;
+    const int64_t first = TRANS ? ncalls : 0, last = TRANS ? 2 * ncalls : ncalls;  // tasks
+    const int64_t base = q.pack_prefix[first], total = q.pack_prefix[last];        // chunks
     const uint32_t p = q.hdr->p;
     const int32_t H = int32_t(limb_threshold(L));
-    int64_t lo = 0;
+    int64_t lo = first;
     for (;;) {
         if (threadIdx.x == 0)
-            chunk_s = int64_t(atomicAdd((unsigned long long *)counter, (unsigned long long)kGrab));
+            chunk_s = base + int64_t(atomicAdd((unsigned long long *)counter,
+                                               (unsigned long long)kGrab));
         __syncthreads();
         const int64_t c0 = chunk_s;
         __syncthreads();
         if (c0 >= total) break;
-        lo = find_from(q.pack_prefix, npack, lo, c0);
+        lo = find_from(q.pack_prefix, last, lo, c0);
         const int64_t c1 = c0 + kGrab < total ? c0 + kGrab : total;
         for (int64_t c = c0; c < c1; ++c) {
             while (q.pack_prefix[lo + 1] <= c) ++lo;  // the next chunks may start the next operand
@@ -224,12 +230,8 @@ __global__ __launch_bounds__(256) void k_pack_limb_batched(QueueView q, uint64_t
             const int64_t kchunks = (t.nkb + 1) / 2;
             const int64_t rho0 = (local / kchunks) * kChunk, kap0 = (local % kchunks) * kChunk;
             if (c > c0) __syncthreads();  // the previous chunk's LDS reads are done
-            if (t.trans)
-                pack_chunk<L, true>(t.dst, t.nkb, t.src, t.r0, t.c0, t.shift, t.R, t.K, t.logT, p,
-                                    H, rho0, kap0, tile, t.neg);
-            else
-                pack_chunk<L, false>(t.dst, t.nkb, t.src, t.r0, t.c0, t.shift, t.R, t.K, t.logT, p,
-                                     H, rho0, kap0, tile, t.neg);
+            pack_chunk<L, TRANS>(t.dst, t.nkb, t.src, t.r0, t.c0, t.shift, t.R, t.K, t.logT, p, H,
+                                 rho0, kap0, tile, t.neg);
         }
     }
 }
@@ -263,22 +265,30 @@ hipError_t launch_pack_u32(uint32_t *dst, int64_t prow, int64_t pcol, const uint
     return hipGetLastError();
 }
 
-hipError_t launch_pack_limb_batched(int L, const QueueView &q, uint64_t *counter, int num_cu,
+hipError_t launch_pack_limb_batched(int L, const QueueView &q, uint64_t *counters, int num_cu,
                                     hipStream_t s)
 {
-    auto go = [&](auto kern) {
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-        hipLaunchKernelGGL(kern, dim3(unsigned(num_cu * per_cu)), dim3(256), 0, s, q, counter);
-        return hipGetLastError();
+    // A panels with counters[0], then B panels with counters[1].
+    auto go = [&](auto kern_a, auto kern_b) {
+        hipError_t e = hipSuccess;
+        int i = 0;
+        for (auto kern : {kern_a, kern_b}) {
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) !=
+                    hipSuccess ||
+                per_cu < 1)
+                per_cu = 1;
+            hipLaunchKernelGGL(kern, dim3(unsigned(num_cu * per_cu)), dim3(256), 0, s, q,
+                               counters + i++);
+            if ((e = hipGetLastError()) != hipSuccess) break;
+        }
+        return e;
     };
     switch (L) {
-    case 1: return go(k_pack_limb_batched<1>);
-    case 2: return go(k_pack_limb_batched<2>);
-    case 3: return go(k_pack_limb_batched<3>);
-    default: return go(k_pack_limb_batched<4>);
+    case 1: return go(k_pack_limb_batched<1, false>, k_pack_limb_batched<1, true>);
+    case 2: return go(k_pack_limb_batched<2, false>, k_pack_limb_batched<2, true>);
+    case 3: return go(k_pack_limb_batched<3, false>, k_pack_limb_batched<3, true>);
+    default: return go(k_pack_limb_batched<4, false>, k_pack_limb_batched<4, true>);
     }
 }
 
