@@ -354,7 +354,7 @@ extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, in
         cfg = tune_get(ctx, tune_key_batch(L, T, plans));
         if (cfg < 0 && ctx->autotune == 2) cfg = tune_batch(ctx, plans, L, p, stream);
     }
-    if (cfg < 0) cfg = batch_cfg(L, plans);
+    if (!limb_cfg_fits(L, cfg)) cfg = batch_cfg(L, plans);  // none cached, or unusable for L
     for (size_t q = 0; q < live.size(); ++q) {
         plan_product(prods[live[q]], MH_MODE_LIMB_I8, plans[q], cfg);
         plans[q].sub = sub;

@@ -378,7 +378,8 @@ void plan_product(const Product &p, int mode, Plan &pl, int forced_cfg)
             if (limb_cfg_fits(pl.L, c))
                 pl.limb_cfg = c;
         }
-        if (forced_cfg >= 0) pl.limb_cfg = forced_cfg;
+        // a forced configuration (tuner, tune cache) that does not fit L is ignored
+        if (limb_cfg_fits(pl.L, forced_cfg)) pl.limb_cfg = forced_cfg;
         const LimbKernelCfg &c = limb_cfg(pl.limb_cfg);
         pl.tile_m = c.tile_m();
         pl.tile_n = c.tile_n();

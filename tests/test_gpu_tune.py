@@ -84,3 +84,31 @@ def test_tune_batched(mh):
             assert np.array_equal(host_of(to_cart(mh, ctx, Cd, N, T)), C), rep
     finally:
         mh.mh_ctx_destroy(ctx)
+
+
+def test_cached_configuration_that_does_not_fit_is_ignored(mh, tmp_path):
+    # A cache entry naming configuration 3 (128 x 128 blocks, built for at
+    # most two limbs) for a four-limb bucket: the product falls back to the
+    # built-in choice and stays exact.
+    torch_cuda()
+    p, T, N = 2**31 - 1, 64, 1024
+    P = (3, 70, 10, 20, 30, 40, 500, 600, 450)
+    ctx = mh.mh_ctx_create(0)
+    try:
+        tag_path = str(tmp_path / "probe.json")
+        mh.check(mh.mh_ctx_tune_cache_save(ctx, tag_path))
+        device_line = [l for l in open(tag_path) if '"device"' in l][0]
+        key = "single L=4 T=64 m=9 k=10 n=9"
+        path = str(tmp_path / "bad.json")
+        with open(path, "w") as f:
+            f.write(device_line)
+            f.write(' "entries": [\n  {"key": "%s", "cfg": 3, "ms": 1.0}\n ]}\n' % key)
+        s, n = mh.mh_ctx_tune_cache_load(ctx, path)
+        assert s == mh.MH_OK and n == 1
+        assert mh.mh_ctx_tune_lookup(ctx, p, T, 500, 600, 450) == 3
+        mh.check(mh.mh_ctx_set_autotune(ctx, 1))  # use the cache, never tune
+        got, want = _product(mh, ctx, p, T, N, P, (81, 82, 83))
+        assert np.array_equal(got, want)
+        assert mh.mh_ctx_last_device_error(ctx) == 0
+    finally:
+        mh.mh_ctx_destroy(ctx)
