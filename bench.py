@@ -255,6 +255,7 @@ def main():
     stream.synchronize()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    gemm_each = mh.mh_ctx_kernel_times(ctx, mh.MH_K_GEMM_LIMB)
     gemm_ms, gemm_n = mh.mh_ctx_kernel_time(ctx, mh.MH_K_GEMM_LIMB, reset=True)
     tuned = mh.mh_ctx_tune_lookup(ctx, p, T, m, k, n)
     kernel_cfg = tuned if tuned >= 0 else info.kernel_cfg
@@ -335,6 +336,9 @@ def main():
                      "traffic": recorded_traffic("k_gemm_limb", kernel_cfg, args.workload),
                      "kernel": "k_gemm_limb", "kernel_cfg": kernel_cfg,
                      "kernel_src": kernel_source_hash(), "kernel_ms": gemm_avg,
+                     "kernel_ms_min": min(gemm_each) if gemm_each else None,
+                     "kernel_ms_median": (sorted(gemm_each)[len(gemm_each) // 2]
+                                          if gemm_each else None),
                      "note": "achieved = int8 ops (L^2 * 2mnk) per launch / average launch "
                              "time; traffic = HBM bytes per launch from FETCH_SIZE and "
                              "WRITE_SIZE, copy-calibrated"},

@@ -96,11 +96,12 @@ enum {
 enum {
     MH_K_LAYOUT_FROM = 0,
     MH_K_LAYOUT_TO = 1,
-    MH_K_PACK = 2,         /* operand packing (limb split or u32 panel copy) */
+    MH_K_PACK = 2,         /* operand packing of one product, A and B together
+                              (limb split or u32 panel copy) */
     MH_K_GEMM_PLAIN = 3,
     MH_K_GEMM_LIMB = 4,
     MH_K_BATCHED = 5,      /* one batched graph: persistent pack + persistent GEMM */
-    MH_K_GEMM_F64 = 6,
+    MH_K_GEMM_F64 = 6,     /* FP64-MFMA form (plain and elementwise forms: MH_K_GEMM_PLAIN) */
     MH_K_COUNT = 7
 };
 
@@ -129,6 +130,13 @@ mh_status mh_ctx_set_timing(mh_ctx *ctx, int enable);
  * events have completed.  reset != 0 clears the record afterwards. */
 mh_status mh_ctx_kernel_time(mh_ctx *ctx, int kernel, double *total_ms, int64_t *launches,
                              int reset);
+
+/* The individual durations (ms, in launch order) of kernel class `kernel`
+ * since the last reset: at most `cap` are written to ms_out (host array),
+ * *launches is set to the number recorded.  Blocks like mh_ctx_kernel_time;
+ * does not reset. */
+mh_status mh_ctx_kernel_times(mh_ctx *ctx, int kernel, double *ms_out, int64_t cap,
+                              int64_t *launches);
 
 /* Autotuning of the limb kernels' configuration (workgroup and wave tile,
  * pipeline depth, LDS sharing) per shape bucket: single products by limbs,

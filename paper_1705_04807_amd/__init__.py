@@ -58,7 +58,7 @@ EXPORTS = (
     "mh_matmul_modp", "mh_matmul_modp_batched", "mh_plan_describe", "mh_plan_leaves",
     "mh_plan_gemm_tasks", "mh_ctx_set_autotune", "mh_ctx_tune_lookup", "mh_ctx_tune_cache_save",
     "mh_ctx_tune_cache_load", "mh_parent_size", "mh_layout_from_cartesian_padded",
-    "mh_layout_to_cartesian_padded",
+    "mh_layout_to_cartesian_padded", "mh_ctx_kernel_times",
 )
 
 
@@ -106,6 +106,8 @@ def _load():
         "mh_ctx_set_timing": ([P, ct.c_int], ct.c_int),
         "mh_ctx_kernel_time": ([P, ct.c_int, ct.POINTER(ct.c_double), ct.POINTER(I64), ct.c_int],
                                ct.c_int),
+        "mh_ctx_kernel_times": ([P, ct.c_int, ct.POINTER(ct.c_double), I64, ct.POINTER(I64)],
+                                ct.c_int),
         "mh_ctx_set_autotune": ([P, ct.c_int], ct.c_int),
         "mh_ctx_tune_lookup": ([P, U32, I32, I64, I64, I64, ct.POINTER(I32)], ct.c_int),
         "mh_ctx_tune_cache_save": ([P, ct.c_char_p], ct.c_int),
@@ -171,6 +173,14 @@ def mh_ctx_kernel_time(ctx: int, kernel: int, reset: bool = False) -> tuple[floa
     check(lib.mh_ctx_kernel_time(ctx, kernel, ct.byref(ms), ct.byref(n), 1 if reset else 0),
           "mh_ctx_kernel_time")
     return ms.value, n.value
+
+
+def mh_ctx_kernel_times(ctx: int, kernel: int, cap: int = 4096) -> list[float]:
+    """Durations (ms) of the recorded launches of one kernel class, in launch order."""
+    buf = (ct.c_double * max(cap, 1))()
+    n = ct.c_int64()
+    check(lib.mh_ctx_kernel_times(ctx, kernel, buf, cap, ct.byref(n)), "mh_ctx_kernel_times")
+    return [buf[i] for i in range(min(cap, n.value))]
 
 
 def mh_ctx_set_autotune(ctx: int, mode: int) -> int:

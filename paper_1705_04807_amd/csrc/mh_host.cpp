@@ -200,6 +200,25 @@ extern "C" mh_status mh_ctx_kernel_time(mh_ctx *ctx, int kernel, double *total_m
     return MH_OK;
 }
 
+extern "C" mh_status mh_ctx_kernel_times(mh_ctx *ctx, int kernel, double *ms_out, int64_t cap,
+                                         int64_t *launches)
+{
+    if (!ctx || kernel < 0 || kernel >= MH_K_COUNT || cap < 0 || (cap > 0 && !ms_out))
+        return MH_E_INVALID;
+    DeviceGuard g(ctx->device);
+    int64_t cnt = 0;
+    for (auto &r : ctx->records) {
+        if (r.kernel != kernel) continue;
+        if (hipEventSynchronize(r.b) != hipSuccess) return note_error(ctx, hipErrorUnknown);
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+        if (cnt < cap) ms_out[cnt] = ms;
+        ++cnt;
+    }
+    if (launches) *launches = cnt;
+    return MH_OK;
+}
+
 // ================================================================ index math
 
 namespace mh {

@@ -29,6 +29,14 @@ def test_header_symbols_exported():
         assert hasattr(mh.lib, n), n
 
 
+def test_null_context_is_rejected():
+    for call in (lambda: mh.lib.mh_ctx_kernel_times(None, 0, None, 0, None),
+                 lambda: mh.lib.mh_ctx_set_timing(None, 1),
+                 lambda: mh.lib.mh_ctx_set_autotune(None, 1),
+                 lambda: mh.lib.mh_ctx_destroy(None)):
+        assert call() == mh.MH_E_INVALID
+
+
 def test_status_strings():
     for s in range(0, 9):
         assert mh.mh_status_string(s)
