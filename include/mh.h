@@ -34,6 +34,11 @@
  *    workspace (limb panels, task queues, captured graphs); nothing the
  *    library allocates is visible to the caller.
  *  - No C++ exception crosses this interface.
+ *  - Two environment variables override the limb form's choices, for
+ *    tuning and testing: MH_LIMB_CFG=<index> forces a kernel configuration
+ *    (ignored if it does not fit the limb count) and MH_LIMB_KBLOCK=<depth>
+ *    (a multiple of 64) shortens the k-blocks between reductions below the
+ *    int32 bound.  Both keep results exact.
  */
 #ifndef MH_H
 #define MH_H
