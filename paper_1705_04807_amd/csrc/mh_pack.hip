@@ -111,7 +111,7 @@ __device__ __forceinline__ void pack_chunk(int8_t *__restrict__ dst, int64_t nkb
     //           c0 + rho - shift), other = depth kap (source row r0 + kap).
     {
         const int64_t cfirst = TRANS ? c0 + rho0 - shift : c0 + kap0;  // source col of slot 0
-        const int64_t clo = TRANS ? c0 : c0;                            // block's columns:
+        const int64_t clo = c0;                                         // block's columns:
         const int64_t chi = TRANS ? c0 + R : c0 + K;                    //   [clo, chi)
         const int64_t gbase = cfirst & ~int64_t(3);
         const int mis = int(cfirst - gbase);

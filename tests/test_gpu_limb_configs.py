@@ -17,6 +17,7 @@ pytestmark = pytest.mark.gpu
 
 PRIMES = {1: 251, 2: 65521, 3: (1 << 24) - 3, 4: 2**31 - 1}
 N, T = 1024, 64
+NCFG = 16  # entries of the configuration table
 OFF = dict(rc=17, cc=40, ra=3, ca=100, rb=60, cb=7, m=300, k=700, n=333)
 
 
@@ -47,7 +48,7 @@ def operands(mh, ctx):
 
 
 @pytest.mark.parametrize("kblock", [None, 128])
-@pytest.mark.parametrize("cfg", range(16))
+@pytest.mark.parametrize("cfg", range(NCFG))
 @pytest.mark.parametrize("L", [1, 2, 3, 4])
 def test_configuration(mh, ctx, operands, monkeypatch, L, cfg, kblock):
     p = PRIMES[L]

@@ -181,6 +181,25 @@ def test_limbs_and_kblock():
         assert (info.kblock + 64) * L * 2**14 >= 2**31
 
 
+def test_forced_configuration_table(monkeypatch):
+    """MH_LIMB_CFG is honoured for every entry of the configuration table
+    that fits the limb count, and ignored beyond it; the GPU parity test of
+    the configurations covers exactly this table."""
+    from tests.test_gpu_limb_configs import NCFG
+    big = dict(NC=2048, NA=2048, NB=2048, m=2048, k=2048, n=2048, mode=mh.MH_MODE_LIMB_I8)
+    for cfg in range(NCFG + 4):
+        monkeypatch.setenv("MH_LIMB_CFG", str(cfg))
+        s, info = describe(p=251, **big)
+        assert s == 0
+        assert (info.kernel_cfg == cfg) == (cfg < NCFG), cfg
+    # L = 4 keeps only the configurations whose accumulators fit
+    fits4 = set()
+    for cfg in range(NCFG):
+        monkeypatch.setenv("MH_LIMB_CFG", str(cfg))
+        fits4 |= {cfg} if describe(p=2**31 - 1, **big)[1].kernel_cfg == cfg else set()
+    assert {0, 1, 2, 4, 6, 7, 9, 10, 11, 12} == fits4
+
+
 # ------------------------------------------------------------------ planner
 
 def _leaf_count_brute(T, rc, cc, ra, ca, rb, cb, m, k, n):
