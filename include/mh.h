@@ -143,6 +143,24 @@ mh_status mh_ctx_kernel_time(mh_ctx *ctx, int kernel, double *total_ms, int64_t 
 mh_status mh_ctx_kernel_times(mh_ctx *ctx, int kernel, double *ms_out, int64_t cap,
                               int64_t *launches);
 
+/* ------------------------------------------------------------ diagnostics */
+
+/* Sustained int8 MFMA rate of the context's device, the ceiling a dense
+ * int8 kernel can approach there: one workgroup of four waves per compute
+ * unit keeps eight independent 32x32 accumulators busy with
+ * v_mfma_i32_32x32x32_i8 on random register operands, rotated from one
+ * MFMA to the next, with no memory traffic in the loop; each wave issues
+ * 8 * iters MFMAs.  One untimed launch of the same size runs first (the
+ * clock settles under the load), then the timed one, bracketed by HIP
+ * events on `stream`.  *pops receives int8 operations per second
+ * (2 x 32^3 per MFMA).  The published peak assumes the full engine clock;
+ * under this load the device may lower its clock to stay within its power
+ * limit, which this figure includes.  Synchronises `stream`; allocates and
+ * frees a small device buffer.
+ * Errors: MH_E_INVALID (ctx or pops null; iters odd, below 2 or above
+ * 2^24), MH_E_NOMEM, MH_E_DEVICE. */
+mh_status mh_probe_mfma_i8(mh_ctx *ctx, int32_t iters, double *pops, hipStream_t stream);
+
 /* Autotuning of the limb kernels' configuration (workgroup and wave tile,
  * pipeline depth, LDS sharing) per shape bucket: single products by limbs,
  * T and ceil(log2) of m, k, n; batches by limbs, T and ceil(log2) of their

@@ -58,7 +58,7 @@ EXPORTS = (
     "mh_matmul_modp", "mh_matmul_modp_batched", "mh_plan_describe", "mh_plan_leaves",
     "mh_plan_gemm_tasks", "mh_ctx_set_autotune", "mh_ctx_tune_lookup", "mh_ctx_tune_cache_save",
     "mh_ctx_tune_cache_load", "mh_parent_size", "mh_layout_from_cartesian_padded",
-    "mh_layout_to_cartesian_padded", "mh_ctx_kernel_times",
+    "mh_layout_to_cartesian_padded", "mh_ctx_kernel_times", "mh_probe_mfma_i8",
 )
 
 
@@ -108,6 +108,7 @@ def _load():
                                ct.c_int),
         "mh_ctx_kernel_times": ([P, ct.c_int, ct.POINTER(ct.c_double), I64, ct.POINTER(I64)],
                                 ct.c_int),
+        "mh_probe_mfma_i8": ([P, I32, ct.POINTER(ct.c_double), P], ct.c_int),
         "mh_ctx_set_autotune": ([P, ct.c_int], ct.c_int),
         "mh_ctx_tune_lookup": ([P, U32, I32, I64, I64, I64, ct.POINTER(I32)], ct.c_int),
         "mh_ctx_tune_cache_save": ([P, ct.c_char_p], ct.c_int),
@@ -173,6 +174,14 @@ def mh_ctx_kernel_time(ctx: int, kernel: int, reset: bool = False) -> tuple[floa
     check(lib.mh_ctx_kernel_time(ctx, kernel, ct.byref(ms), ct.byref(n), 1 if reset else 0),
           "mh_ctx_kernel_time")
     return ms.value, n.value
+
+
+def mh_probe_mfma_i8(ctx: int, iters: int, stream: int) -> float:
+    """Sustained int8 MFMA operations per second of the context's device
+    (random register operands, no memory traffic; see include/mh.h)."""
+    pops = ct.c_double()
+    check(lib.mh_probe_mfma_i8(ctx, iters, ct.byref(pops), stream), "mh_probe_mfma_i8")
+    return pops.value
 
 
 def mh_ctx_kernel_times(ctx: int, kernel: int, cap: int = 4096) -> list[float]:
