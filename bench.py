@@ -6,7 +6,9 @@ HBM in Morton-hybrid layout.  Prints one JSON line:
   value  = modular GOPS (2mnk / s) of the timed steps, whole job;
   roofline = the dominant kernel (the limb GEMM) against the int8 MFMA peak,
              its average duration taken from HIP events the library records
-             on the stream it launches on;
+             on the stream it launches on; beside the published peak,
+             sustained_peak = the int8 MFMA rate the device keeps up under
+             its power limit (mh_probe_mfma_i8, after the timed region);
   plain  = the plain uint32 kernel on the same workload (the comparator);
   fp64   = the FP64-MFMA form on the same workload, when p < 2^26;
   cpu_baseline = the CPU oracle (triple loop, 128-bit accumulators) on a
