@@ -203,9 +203,12 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
         constexpr int NA = WM * WAVES_M * KS * L;
         constexpr int NBLK = (WM * WAVES_M + WN * WAVES_N) * KS * L;
         constexpr int R = (NBLK + NW - 1) / NW;  // 16-byte loads per wave and stage (at most)
-        // With more than two buffers, the wait below counts this wave's loads
-        // of the later stages, so every wave must issue the same number.
-        static_assert(NBUF == 2 || (NBLK % NW == 0 && (NBUF - 2) * R < 64), "vmcnt count");
+        // With more than two buffers, the wait below lets this wave's loads of
+        // the later stages stay outstanding; waves issue R or R - 1 loads per
+        // stage, so it counts the smaller number (waiting a little longer
+        // where a wave issued more is still correct).
+        constexpr int RMIN = NBLK / NW;
+        static_assert((NBUF - 2) * RMIN < 64, "vmcnt count");
         const int wv = __builtin_amdgcn_readfirstlane(wave);
         const int64_t slabA0 = gm * (WM * WAVES_M), slabB0 = gn * (WN * WAVES_N);
         // Block addresses are wave-uniform (scalar registers); only the lane's
@@ -234,58 +237,88 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
                 }
             });
         };
-        // s_waitcnt vmcnt(n) with expcnt and lgkmcnt left free
-        constexpr int kWaitInFlight = ((NBUF - 2) * R & 15) | (7 << 4) | (15 << 8) |
-                                      (((NBUF - 2) * R >> 4) << 14);
+        // s_waitcnt vmcnt(n) lgkmcnt(0), expcnt left free
+        constexpr int kWaitInFlight = ((NBUF - 2) * RMIN & 15) | (7 << 4) |
+                                      (((NBUF - 2) * RMIN >> 4) << 14);
+        constexpr int kWaitAll = 7 << 4;  // vmcnt(0) lgkmcnt(0)
+        static_assert(KS % 2 == 0, "fragment sets alternate within and across stages");
         const int64_t nst = nkb / KS, st_red = a.kb_per_red / KS;
+
+        // Make stage s readable: this wave's blocks of s have landed (loads
+        // complete in order, so it suffices that at most the NBUF - 2 later
+        // stages are outstanding; the last stages, and the first stage after
+        // an epilogue, whose C accesses were issued after the prefetches,
+        // wait for everything), and its own LDS reads of the previous stage
+        // are done; then every wave has done the same, so buffer (s - 1) mod
+        // NBUF is free again and stage s + NBUF - 1 goes into it.  A bare
+        // barrier: the fence of __syncthreads() would make the compiler wait
+        // for the later stages' loads as well.  The empty asm statements keep
+        // memory accesses on their side.
+        auto enter_stage = [&](int64_t s, bool after_epilogue) {
+            if (NBUF > 2 && s + NBUF - 2 < nst && !after_epilogue)
+                __builtin_amdgcn_s_waitcnt(kWaitInFlight);
+            else
+                __builtin_amdgcn_s_waitcnt(kWaitAll);
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            if (s + NBUF - 1 < nst) issue(s + NBUF - 1, int((s + NBUF - 1) % NBUF));
+        };
+        // Fragments of k-block q of stage s, from LDS.
+        using FragA1 = v4i[WM][L];
+        using FragB1 = v4i[WN][L];
+        auto read = [&](FragA1 &fa, FragB1 &fb, int64_t s, int q) {
+            const v4i *sb = lds_buf + (s % NBUF) * (NBLK * 64) + lane;
+            static_for<WM>([&](auto i) {
+                static_for<L>([&](auto t) {
+                    fa[i][t] = sb[(((wmi * WM + i) * KS + q) * L + t) * 64];
+                });
+            });
+            static_for<WN>([&](auto j) {
+                static_for<L>([&](auto u) {
+                    fb[j][u] = sb[(NA + ((wni * WN + j) * KS + q) * L + u) * 64];
+                });
+            });
+        };
+        auto mma1 = [&](const FragA1 &fa, const FragB1 &fb) {
+            static_for<L>([&](auto t) {
+                static_for<L>([&](auto u) {
+                    static_for<WM>([&](auto i) {
+                        static_for<WN>([&](auto j) {
+                            acc[t + u][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                fa[i][t], fb[j][u], acc[t + u][i][j], 0, 0, 0);
+                        });
+                    });
+                });
+            });
+        };
+
         // NBUF - 1 stages in flight ahead of the one being multiplied
         static_for<NBUF - 1>([&](auto s0) {
             if (int64_t(s0) < nst) issue(int64_t(s0), int(s0));
         });
+        // Two fragment sets: the LDS reads of the next k-block (of this
+        // stage, or the first of the next one) are in flight while the
+        // current one's MFMAs run; the next stage is entered before the last
+        // k-block of the current one is multiplied.
+        FragA1 fa[2];
+        FragB1 fb[2];
         for (int64_t st0 = 0; st0 < nst; st0 += st_red) {
             const int64_t st1 = (st0 + st_red < nst) ? st0 + st_red : nst;
+            enter_stage(st0, st0 > 0);
+            read(fa[0], fb[0], st0, 0);
             for (int64_t st = st0; st < st1; ++st) {
-                // This wave's blocks of stage st landed.  Loads complete in
-                // order, so it suffices that at most the NBUF - 2 later stages
-                // are outstanding; the last stages, and the first stage after
-                // an epilogue (whose C accesses were issued after the
-                // prefetches), wait for everything.
-                if (NBUF > 2 && st + NBUF - 2 < nst && !(st == st0 && st0 > 0))
-                    __builtin_amdgcn_s_waitcnt(kWaitInFlight);
-                else
-                    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-                // Every wave's did, and buffer (st - 1) mod NBUF is free again.
-                // A bare barrier: the wait above already covers this wave's
-                // loads into LDS, and the fence of __syncthreads() would make
-                // the compiler wait for the later stages' loads as well.  The
-                // empty asm statements keep memory accesses on their side.
-                asm volatile("" ::: "memory");
-                __builtin_amdgcn_s_barrier();
-                asm volatile("" ::: "memory");
-                if (st + NBUF - 1 < nst) issue(st + NBUF - 1, int((st + NBUF - 1) % NBUF));
-                const v4i *sb = lds_buf + (st % NBUF) * (NBLK * 64) + lane;
                 static_for<KS>([&](auto q) {
-                    v4i fa[WM][L], fb[WN][L];
-                    static_for<WM>([&](auto i) {
-                        static_for<L>([&](auto t) {
-                            fa[i][t] = sb[(((wmi * WM + i) * KS + q) * L + t) * 64];
-                        });
-                    });
-                    static_for<WN>([&](auto j) {
-                        static_for<L>([&](auto u) {
-                            fb[j][u] = sb[(NA + ((wni * WN + j) * KS + q) * L + u) * 64];
-                        });
-                    });
-                    static_for<L>([&](auto t) {
-                        static_for<L>([&](auto u) {
-                            static_for<WM>([&](auto i) {
-                                static_for<WN>([&](auto j) {
-                                    acc[t + u][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                        fa[i][t], fb[j][u], acc[t + u][i][j], 0, 0, 0);
-                                });
-                            });
-                        });
-                    });
+                    constexpr int cur = int(q) & 1, nxt = cur ^ 1;
+                    if constexpr (int(q) + 1 < KS) {
+                        read(fa[nxt], fb[nxt], st, int(q) + 1);
+                    } else {
+                        if (st + 1 < st1) {
+                            enter_stage(st + 1, false);
+                            read(fa[nxt], fb[nxt], st + 1, 0);
+                        }
+                    }
+                    mma1(fa[cur], fb[cur]);
                 });
             }
             flush();
