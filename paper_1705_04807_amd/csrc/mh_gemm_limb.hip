@@ -29,7 +29,9 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 // One workgroup's output block (gm, gn) of the product described by `a`.
-template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF>
+// PIPE (LDS path): fragment reads one k-block ahead of the MFMAs, with a
+// second fragment set.
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF, bool PIPE>
 __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t gn)
 {
     constexpr int S = 2 * L - 1;
@@ -297,31 +299,48 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
         static_for<NBUF - 1>([&](auto s0) {
             if (int64_t(s0) < nst) issue(int64_t(s0), int(s0));
         });
-        // Two fragment sets: the LDS reads of the next k-block (of this
-        // stage, or the first of the next one) are in flight while the
-        // current one's MFMAs run; the next stage is entered before the last
-        // k-block of the current one is multiplied.
-        FragA1 fa[2];
-        FragB1 fb[2];
-        for (int64_t st0 = 0; st0 < nst; st0 += st_red) {
-            const int64_t st1 = (st0 + st_red < nst) ? st0 + st_red : nst;
-            enter_stage(st0, st0 > 0);
-            read(fa[0], fb[0], st0, 0);
-            for (int64_t st = st0; st < st1; ++st) {
-                static_for<KS>([&](auto q) {
-                    constexpr int cur = int(q) & 1, nxt = cur ^ 1;
-                    if constexpr (int(q) + 1 < KS) {
-                        read(fa[nxt], fb[nxt], st, int(q) + 1);
-                    } else {
-                        if (st + 1 < st1) {
-                            enter_stage(st + 1, false);
-                            read(fa[nxt], fb[nxt], st + 1, 0);
+        if constexpr (PIPE) {
+            // Two fragment sets: the LDS reads of the next k-block (of this
+            // stage, or the first of the next one) are in flight while the
+            // current one's MFMAs run; the next stage is entered before the
+            // last k-block of the current one is multiplied.
+            FragA1 fa[2];
+            FragB1 fb[2];
+            for (int64_t st0 = 0; st0 < nst; st0 += st_red) {
+                const int64_t st1 = (st0 + st_red < nst) ? st0 + st_red : nst;
+                enter_stage(st0, st0 > 0);
+                read(fa[0], fb[0], st0, 0);
+                for (int64_t st = st0; st < st1; ++st) {
+                    static_for<KS>([&](auto q) {
+                        constexpr int cur = int(q) & 1, nxt = cur ^ 1;
+                        if constexpr (int(q) + 1 < KS) {
+                            read(fa[nxt], fb[nxt], st, int(q) + 1);
+                        } else {
+                            if (st + 1 < st1) {
+                                enter_stage(st + 1, false);
+                                read(fa[nxt], fb[nxt], st + 1, 0);
+                            }
                         }
-                    }
-                    mma1(fa[cur], fb[cur]);
-                });
+                        mma1(fa[cur], fb[cur]);
+                    });
+                }
+                flush();
             }
-            flush();
+        } else {
+            // One fragment set, read right before its MFMAs.
+            for (int64_t st0 = 0; st0 < nst; st0 += st_red) {
+                const int64_t st1 = (st0 + st_red < nst) ? st0 + st_red : nst;
+                for (int64_t st = st0; st < st1; ++st) {
+                    enter_stage(st, st == st0 && st0 > 0);
+                    static_for<KS>([&](auto q) {
+                        FragA1 fa;
+                        FragB1 fb;
+                        read(fa, fb, st, int(q));
+                        mma1(fa, fb);
+                    });
+                }
+                flush();
+            }
         }
     }
 }
@@ -331,7 +350,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb(LimbArgs a
 {
     int64_t gm, gn;
     tile_of(blockIdx.x, a.grid_m, a.grid_n, 8, gm, gn);
-    gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>(a, gm, gn);
+    gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, true>(a, gm, gn);
 }
 
 // Persistent form for a batch of products: every workgroup pops output
@@ -356,8 +375,11 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb_batched(Qu
         lo = find_from(q.tile_prefix, ncalls, lo, t);
         const LimbArgs a = q.calls[lo];
         const int64_t local = t - q.tile_prefix[lo];
-        gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>(a, local / a.grid_n,
-                                                             local % a.grid_n);
+        // The queue state takes registers: only the eight-wave 32 x 32
+        // configurations have room for the second fragment set here.
+        constexpr bool kPipe = WAVES_M * WAVES_N <= 8 && WM * WN == 1;
+        gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, kPipe>(a, local / a.grid_n,
+                                                                    local % a.grid_n);
     }
 }
 
