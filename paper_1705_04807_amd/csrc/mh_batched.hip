@@ -7,11 +7,13 @@
 //   reset counters -> persistent pack kernels (A, then B panels) ->
 //   persistent GEMM kernel
 // on one stream.  Each persistent kernel has a fixed grid (CUs x occupancy)
-// and pops work items through an atomic counter until the queue is empty,
+// and pops work items through atomic counters until the queue is empty,
 // so the graph's topology never changes: a new batch only rewrites the
 // queue (one host-to-device copy from pinned staging memory) before the
-// graph is launched again.  Products are queued largest k first, so the
-// longest output blocks start first (longest-processing-time order).
+// graph is launched again.  The products are split into one group per XCD,
+// balanced by work, so that each group's operand panels are read through
+// one L2; within a group they are queued largest k first, so the longest
+// output blocks start first (longest-processing-time order).
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
@@ -35,8 +37,9 @@ int batch_cfg(int L, const std::vector<Plan> &plans)
     double area = 0.0;
     for (const Plan &p : plans) area += double(p.pr.m) * double(p.pr.n);
     area /= std::max<size_t>(plans.size(), 1);
-    // Small per-product tiles keep padding and tails low for uneven batches.
-    int cfg = (L <= 2 || area <= 512.0 * 512.0) ? 6 : 4;
+    // 128 x 128 blocks of 16 waves when the products are large enough (L <=
+    // 2); else small per-product blocks keep padding and tails low.
+    int cfg = area <= 512.0 * 512.0 ? 6 : (L <= 2 ? 13 : 4);
     if (const char *e = std::getenv("MH_LIMB_CFG")) {  // explicit override (tuning runs)
         int c = std::atoi(e);
         if (limb_cfg_fits(L, c))
@@ -180,11 +183,28 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
                        hipStream_t stream, uint32_t *c_override)
 {
     // Longest-processing-time order: every output block of a product costs
-    // its k, so products with the longest k go first.
+    // its k, so products with the longest k go first.  In that order each
+    // product joins the XCD group with the least work so far (blocks x k);
+    // the queue then holds the groups one after another, each in LPT order.
     std::vector<size_t> order(plans.size());
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](size_t a, size_t b) { return plans[a].kpad > plans[b].kpad; });
+    std::vector<int> grp(plans.size());
+    double work[kXcdGroups] = {};
+    int64_t group_tiles[kXcdGroups] = {}, group_calls[kXcdGroups] = {};
+    for (size_t i : order) {
+        int g = 0;
+        for (int h = 1; h < kXcdGroups; ++h)
+            if (work[h] < work[g]) g = h;
+        const int64_t tiles = plans[i].grid_m * plans[i].grid_n;
+        grp[i] = g;
+        work[g] += double(tiles) * double(plans[i].kpad);
+        group_tiles[g] += tiles;
+        group_calls[g] += 1;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return grp[a] < grp[b]; });
 
     // Panels of every product in the context workspace.
     std::vector<size_t> aoff(plans.size()), boff(plans.size());
@@ -257,6 +277,12 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
     h.gemm_tiles = tile_total;
     h.p = p;
     h.L = L;
+    int64_t first_call = 0;
+    for (int g = 0; g < kXcdGroups; ++g) {
+        h.group_tile[g + 1] = h.group_tile[g] + group_tiles[g];
+        h.group_call[g] = std::min<int64_t>(first_call, ncalls - 1);  // unused if empty
+        first_call += group_calls[g];
+    }
 
     s = ensure_graph(ctx, cfg, L);
     if (s != MH_OK) return s;

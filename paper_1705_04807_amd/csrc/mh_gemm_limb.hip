@@ -353,33 +353,61 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb(LimbArgs a
     gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, true>(a, gm, gn);
 }
 
-// Persistent form for a batch of products: every workgroup pops output
-// blocks from the queue through an atomic counter until none is left (the
-// exit test is the same for all waves of the group).  Blocks are numbered
-// call by call in the queue's order (largest k first); a forward search over
-// the per-call prefix sums finds the call of a block.
+// Persistent form for a batch of products.  The output blocks come in
+// kXcdGroups groups of whole products (numbered call by call in the queue's
+// order, largest k first within a group).  Workgroups are dispatched to the
+// XCDs round-robin, so workgroup b runs on XCD b mod 8: it pops blocks of
+// group b mod 8 through that group's atomic counter until the group is
+// done, then helps the other groups in turn, and exits when all are done
+// (the exit test is the same for all waves of the group).  A group's
+// operand panels are thus read by one XCD and stay in its L2.  The pop of
+// the next block is issued when a block starts and read when it ends, so
+// its latency hides behind the block.  A forward search over the per-call
+// prefix sums finds the call of a block.
 template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF>
-__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb_batched(QueueView q,
-                                                                              uint64_t *counter)
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb_batched(
+    const BatchHeader *__restrict__ hdr, const LimbArgs *__restrict__ calls,
+    const int64_t *__restrict__ tile_prefix, uint64_t *counters)
 {
-    __shared__ int64_t task_s;
-    const int64_t total = q.hdr->gemm_tiles;
-    const int64_t ncalls = q.hdr->ncalls;
-    int64_t lo = 0;
-    for (;;) {
-        if (threadIdx.x == 0) task_s = int64_t(atomicAdd((unsigned long long *)counter, 1ull));
+    // (The queue arrays are separate read-only parameters, so that loads
+    // from them at uniform addresses can be scalar.)
+    __shared__ uint32_t task_s;
+    const int64_t ncalls = hdr->ncalls;
+    const int g0 = int(blockIdx.x % kXcdGroups);
+    // Block indices and counter values stay below 2^31 (a batch has fewer
+    // output blocks, and each counter passes its group's size at most once
+    // per workgroup).
+    auto pop = [&](int g) {
+        return uint32_t(atomicAdd((unsigned long long *)(counters + g), 1ull));
+    };
+    // The block index is the same for all lanes: read it as a scalar, so
+    // that the product's arguments load into scalar registers.
+    auto publish = [&](uint32_t v) {
+        if (threadIdx.x == 0) task_s = v;
         __syncthreads();
-        const int64_t t = task_s;
+        const uint32_t r = __builtin_amdgcn_readfirstlane(task_s);
         __syncthreads();
-        if (t >= total) break;
-        lo = find_from(q.tile_prefix, ncalls, lo, t);
-        const LimbArgs a = q.calls[lo];
-        const int64_t local = t - q.tile_prefix[lo];
-        // The queue state takes registers: only the eight-wave 32 x 32
-        // configurations have room for the second fragment set here.
-        constexpr bool kPipe = WAVES_M * WAVES_N <= 8 && WM * WN == 1;
-        gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, kPipe>(a, local / a.grid_n,
-                                                                    local % a.grid_n);
+        return r;
+    };
+    for (int gi = 0; gi < kXcdGroups; ++gi) {
+        const int g = (g0 + gi) % kXcdGroups;
+        const int64_t first = hdr->group_tile[g], size = hdr->group_tile[g + 1] - first;
+        int64_t lo = hdr->group_call[g];
+        uint32_t cur = publish(threadIdx.x == 0 ? pop(g) : 0u);
+        while (int64_t(cur) < size) {
+            uint32_t next = 0;
+            if (threadIdx.x == 0) next = pop(g);  // read after the block
+            const int64_t t = first + cur;
+            lo = find_from(tile_prefix, ncalls, lo, t);
+            const LimbArgs a = calls[lo];
+            const int64_t local = t - tile_prefix[lo];
+            // The queue state takes registers: only the eight-wave 32 x 32
+            // configurations have room for the second fragment set here.
+            constexpr bool kPipe = WAVES_M * WAVES_N <= 8 && WM * WN == 1;
+            gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, kPipe>(a, local / a.grid_n,
+                                                                        local % a.grid_n);
+            cur = publish(next);
+        }
     }
 }
 
@@ -439,7 +467,7 @@ bool cfg_fits(int L, const LimbKernelCfg &c)
 }
 
 template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF = 2>
-hipError_t launch_batched_one(const QueueView &q, uint64_t *counter, int num_cu, hipStream_t s)
+hipError_t launch_batched_one(const QueueView &q, uint64_t *counters, int num_cu, hipStream_t s)
 {
     auto kern = k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>;
     const size_t shm = lds_bytes<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>();
@@ -456,43 +484,43 @@ hipError_t launch_batched_one(const QueueView &q, uint64_t *counter, int num_cu,
             hipSuccess || per_cu < 1)
         per_cu = 1;
     hipLaunchKernelGGL(kern, dim3(unsigned(num_cu * per_cu)), dim3(64 * WAVES_M * WAVES_N), shm,
-                       s, q, counter);
+                       s, q.hdr, q.calls, q.tile_prefix, counters);
     return hipGetLastError();
 }
 
 template <int L>
-hipError_t dispatch_batched_L(int cfg, const QueueView &q, uint64_t *counter, int num_cu,
+hipError_t dispatch_batched_L(int cfg, const QueueView &q, uint64_t *counters, int num_cu,
                               hipStream_t s)
 {
     switch (cfg) {
-    case 0: return launch_batched_one<L, 1, 2, 2, 2, 1, false>(q, counter, num_cu, s);
-    case 1: return launch_batched_one<L, 1, 1, 2, 2, 1, false>(q, counter, num_cu, s);
-    case 2: return launch_batched_one<L, 2, 1, 2, 2, 1, false>(q, counter, num_cu, s);
+    case 0: return launch_batched_one<L, 1, 2, 2, 2, 1, false>(q, counters, num_cu, s);
+    case 1: return launch_batched_one<L, 1, 1, 2, 2, 1, false>(q, counters, num_cu, s);
+    case 2: return launch_batched_one<L, 2, 1, 2, 2, 1, false>(q, counters, num_cu, s);
     case 3:
-        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 1, false>(q, counter, num_cu, s);
+        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 1, false>(q, counters, num_cu, s);
         return hipErrorInvalidValue;
-    case 4: return launch_batched_one<L, 1, 2, 2, 2, 2, false>(q, counter, num_cu, s);
+    case 4: return launch_batched_one<L, 1, 2, 2, 2, 2, false>(q, counters, num_cu, s);
     case 5:
-        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 2, false>(q, counter, num_cu, s);
+        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 2, false>(q, counters, num_cu, s);
         return hipErrorInvalidValue;
-    case 6: return launch_batched_one<L, 1, 1, 2, 2, 2, false>(q, counter, num_cu, s);
-    case 7: return launch_batched_one<L, 1, 2, 2, 2, 2, true>(q, counter, num_cu, s);
+    case 6: return launch_batched_one<L, 1, 1, 2, 2, 2, false>(q, counters, num_cu, s);
+    case 7: return launch_batched_one<L, 1, 2, 2, 2, 2, true>(q, counters, num_cu, s);
     case 8:
-        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 2, true>(q, counter, num_cu, s);
+        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 2, true>(q, counters, num_cu, s);
         return hipErrorInvalidValue;
-    case 9: return launch_batched_one<L, 1, 1, 2, 2, 2, true>(q, counter, num_cu, s);
-    case 10: return launch_batched_one<L, 2, 1, 2, 2, 2, true>(q, counter, num_cu, s);
-    case 11: return launch_batched_one<L, 1, 1, 2, 4, 2, true>(q, counter, num_cu, s);
-    case 12: return launch_batched_one<L, 1, 1, 4, 2, 2, true>(q, counter, num_cu, s);
+    case 9: return launch_batched_one<L, 1, 1, 2, 2, 2, true>(q, counters, num_cu, s);
+    case 10: return launch_batched_one<L, 2, 1, 2, 2, 2, true>(q, counters, num_cu, s);
+    case 11: return launch_batched_one<L, 1, 1, 2, 4, 2, true>(q, counters, num_cu, s);
+    case 12: return launch_batched_one<L, 1, 1, 4, 2, 2, true>(q, counters, num_cu, s);
     case 13:
-        if constexpr (L <= 2) return launch_batched_one<L, 1, 1, 4, 4, 2, true>(q, counter, num_cu, s);
+        if constexpr (L <= 2) return launch_batched_one<L, 1, 1, 4, 4, 2, true>(q, counters, num_cu, s);
         return hipErrorInvalidValue;
     case 14:
         if constexpr (L <= 2)
-            return launch_batched_one<L, 1, 1, 4, 4, 2, true, 3>(q, counter, num_cu, s);
+            return launch_batched_one<L, 1, 1, 4, 4, 2, true, 3>(q, counters, num_cu, s);
         return hipErrorInvalidValue;
     case 15:
-        if constexpr (L <= 2) return launch_batched_one<L, 1, 2, 4, 2, 2, true>(q, counter, num_cu, s);
+        if constexpr (L <= 2) return launch_batched_one<L, 1, 2, 4, 2, 2, true>(q, counters, num_cu, s);
         return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
@@ -551,15 +579,15 @@ int limb_cfg_default(int L, int64_t m, int64_t n, int64_t k)
     return 4;                                  // 64 x 128, register-pipelined
 }
 
-hipError_t launch_gemm_limb_batched(int cfg, int L, const QueueView &q, uint64_t *counter,
+hipError_t launch_gemm_limb_batched(int cfg, int L, const QueueView &q, uint64_t *counters,
                                     int num_cu, hipStream_t s)
 {
     if (cfg < 0 || cfg >= limb_cfg_count() || !cfg_fits(L, kCfgs[cfg])) return hipErrorInvalidValue;
     switch (L) {
-    case 1: return dispatch_batched_L<1>(cfg, q, counter, num_cu, s);
-    case 2: return dispatch_batched_L<2>(cfg, q, counter, num_cu, s);
-    case 3: return dispatch_batched_L<3>(cfg, q, counter, num_cu, s);
-    case 4: return dispatch_batched_L<4>(cfg, q, counter, num_cu, s);
+    case 1: return dispatch_batched_L<1>(cfg, q, counters, num_cu, s);
+    case 2: return dispatch_batched_L<2>(cfg, q, counters, num_cu, s);
+    case 3: return dispatch_batched_L<3>(cfg, q, counters, num_cu, s);
+    case 4: return dispatch_batched_L<4>(cfg, q, counters, num_cu, s);
     }
     return hipErrorInvalidValue;
 }

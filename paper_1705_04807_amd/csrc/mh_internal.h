@@ -283,11 +283,18 @@ struct PackTask {
     int32_t neg, pad;   // neg: pack (p - x) mod p
 };
 
+// Output blocks of a batch are split into kXcdGroups groups of whole
+// products, one per XCD of the device (a persistent workgroup pops its
+// XCD's group first, so the group's operand panels stay in that XCD's L2).
+constexpr int kXcdGroups = 8;
+
 struct BatchHeader {
     int64_t npack, ncalls, pack_chunks, gemm_tiles;
     uint32_t p;
     int32_t L;
-    int64_t pad[2];
+    int64_t group_tile[kXcdGroups + 1];  // group g: output blocks [group_tile[g], group_tile[g+1])
+    int64_t group_call[kXcdGroups];      // first product of group g (queue order)
+    int64_t pad[1];
 };
 
 struct QueueView {
@@ -323,11 +330,12 @@ inline QueueView queue_view(void *base, int64_t cap)
     return q;
 }
 
-// Work counters of one batched graph: A packing, B packing, GEMM.
-constexpr int kBatchCounters = 3;
+// Work counters of one batched graph: A packing, B packing, then one GEMM
+// counter per XCD group.
+constexpr int kBatchCounters = 2 + kXcdGroups;
 hipError_t launch_pack_limb_batched(int L, const QueueView &q, uint64_t *counters, int num_cu,
                                     hipStream_t s);
-hipError_t launch_gemm_limb_batched(int cfg, int L, const QueueView &q, uint64_t *counter,
+hipError_t launch_gemm_limb_batched(int cfg, int L, const QueueView &q, uint64_t *counters,
                                     int num_cu, hipStream_t s);
 hipError_t launch_reset_counters(uint64_t *counters, hipStream_t s);
 
