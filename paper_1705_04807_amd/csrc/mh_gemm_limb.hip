@@ -574,9 +574,9 @@ bool limb_cfg_fits(int L, int idx)
 int limb_cfg_default(int L, int64_t m, int64_t n, int64_t k)
 {
     (void)k;
+    (void)L;
     if (m * n <= int64_t(512) * 512) return 6;  // 64 x 64 output blocks
-    if (L <= 2) return 11;                     // 64 x 128, 8 waves sharing LDS stages
-    return 4;                                  // 64 x 128, register-pipelined
+    return 11;                                 // 64 x 128, 8 waves sharing LDS stages
 }
 
 hipError_t launch_gemm_limb_batched(int cfg, int L, const QueueView &q, uint64_t *counters,
