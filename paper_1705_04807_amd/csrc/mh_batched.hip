@@ -37,9 +37,11 @@ int batch_cfg(int L, const std::vector<Plan> &plans)
     double area = 0.0;
     for (const Plan &p : plans) area += double(p.pr.m) * double(p.pr.n);
     area /= std::max<size_t>(plans.size(), 1);
-    // 128 x 128 blocks of 16 waves when the products are large enough (L <=
-    // 2); else small per-product blocks keep padding and tails low.
-    int cfg = area <= 512.0 * 512.0 ? 6 : (L <= 2 ? 13 : 4);
+    // 64 x 128 blocks of 8 waves sharing LDS stages when the products are
+    // large enough (at L <= 2 two such workgroups share a compute unit, and
+    // one's epilogue overlaps the other's MFMAs); else small per-product
+    // blocks keep padding and tails low.
+    int cfg = area <= 512.0 * 512.0 ? 6 : (L <= 2 ? 11 : 4);
     if (const char *e = std::getenv("MH_LIMB_CFG")) {  // explicit override (tuning runs)
         int c = std::atoi(e);
         if (limb_cfg_fits(L, c))

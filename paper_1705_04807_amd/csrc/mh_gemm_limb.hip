@@ -365,7 +365,9 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb(LimbArgs a
 // its latency hides behind the block.  A forward search over the per-call
 // prefix sums finds the call of a block.
 template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF>
-__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb_batched(
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N,
+                             (WAVES_M * WAVES_N == 8 && WM * WN == 1 && L <= 2) ? 4 : 1) void
+k_gemm_limb_batched(
     const BatchHeader *__restrict__ hdr, const LimbArgs *__restrict__ calls,
     const int64_t *__restrict__ tile_prefix, uint64_t *counters)
 {
@@ -402,8 +404,11 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb_batched(
             const LimbArgs a = calls[lo];
             const int64_t local = t - tile_prefix[lo];
             // The queue state takes registers: only the eight-wave 32 x 32
-            // configurations have room for the second fragment set here.
-            constexpr bool kPipe = WAVES_M * WAVES_N <= 8 && WM * WN == 1;
+            // configurations have room for the second fragment set here, and
+            // at L <= 2 they rather keep to 128 registers (launch bounds), so
+            // that two workgroups share a compute unit and one's epilogue
+            // and first loads overlap the other's MFMAs.
+            constexpr bool kPipe = WAVES_M * WAVES_N <= 8 && WM * WN == 1 && L > 2;
             gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, kPipe>(a, local / a.grid_n,
                                                                         local % a.grid_n);
             cur = publish(next);
