@@ -43,6 +43,7 @@ METRIC = "modular GOPS (2mnk/s) for C+=A·B mod p, MFMA/batched vs plain, bit-ex
 INT8_PEAK_TOPS = 5000.0   # MI355X dense int8 MFMA, 5.0 POP/s
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense fp64 MFMA
 PROBE_ITERS = 40000       # mh_probe_mfma_i8: 8 x 40000 MFMAs per wave, about 7 ms a launch
+VALU_PROBE_ITERS = 8192   # mh_probe_valu_mac: 16 x 8192 per lane, about 7 ms a launch
 # Plain kernel: one multiply-accumulate = v_mad_u64_u32 + v_addc_co_u32, two
 # full-rate VALU instructions; 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz / 2.
 PLAIN_PEAK_TMACS = 256 * 4 * 16 * 2.4e9 / 2 / 1e12
@@ -164,12 +165,12 @@ def cpu_baseline(A_dev, B_dev, W, budget_s=12.0):
     Bh = B_dev[rb:rb + k, cb:cb + n].contiguous().cpu().numpy().view(np.uint32)
     Bh = np.ascontiguousarray(Bh)
 
-    def run(rows):
+    def run(rows, threads=nt):
         Ah = np.ascontiguousarray(
             A_dev[ra:ra + rows, ca:ca + k].contiguous().cpu().numpy().view(np.uint32))
         Ch = np.zeros((rows, n), np.uint32)
         t0 = time.perf_counter()
-        oracle.matmul_modp(Ch, Ah, Bh, p, nthreads=nt)
+        oracle.matmul_modp(Ch, Ah, Bh, p, nthreads=threads)
         return time.perf_counter() - t0
 
     probe = max(1, min(m, nt))
@@ -178,8 +179,13 @@ def cpu_baseline(A_dev, B_dev, W, budget_s=12.0):
     rows = max(probe, (rows // nt) * nt) if rows >= nt else rows
     t = run(rows) if rows != probe else t
     gops = 2.0 * rows * n * k / t / 1e9
+    # the same loop on one thread, over a sample sized to about a fifth of the budget
+    rows1 = max(1, min(m, int(budget_s / 5 * gops * 1e9 / nt / (2.0 * n * k))))
+    t1 = run(rows1, 1)
     return {"value": gops, "unit": "GOPS", "cores": nt, "kind": "oracle", "cpu": cpu_model(),
-            "sample": "%d of %d output rows (all %d columns, k=%d), %.1f s" % (rows, m, n, k, t)}
+            "sample": "%d of %d output rows (all %d columns, k=%d), %.1f s" % (rows, m, n, k, t),
+            "single_thread": {"value": 2.0 * rows1 * n * k / t1 / 1e9, "unit": "GOPS",
+                              "sample": "%d output rows, %.1f s" % (rows1, t1)}}
 
 
 def cpu_model() -> str:
@@ -196,7 +202,7 @@ def cpu_model() -> str:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + [BATCHED])
     ap.add_argument("--plain-steps", type=int, default=2)
@@ -319,6 +325,13 @@ def main():
                               "unit": "T multiply-accumulates/s",
                               "frac": tmacs / PLAIN_PEAK_TMACS, "kernel": "k_gemm_plain"}}
         plain["limb_speedup"] = value / plain["value"]
+        if not args.no_probe:
+            log("sustained multiply-accumulate probe")
+            smacs = max(mh.mh_probe_valu_mac(ctx, VALU_PROBE_ITERS, sh) for _ in range(3)) / 1e12
+            plain["roofline"].update(
+                {"sustained_peak": smacs, "frac_sustained": tmacs / smacs,
+                 "sustained_note": "sustained_peak = issue rate of the same multiply-accumulate "
+                                   "pair with no memory traffic (mh_probe_valu_mac)"})
         log("plain: %.3f ms/step" % plain["ms_per_step"])
 
     # ---- FP64-MFMA form (primes below 2^26 only)

@@ -161,6 +161,18 @@ mh_status mh_ctx_kernel_times(mh_ctx *ctx, int kernel, double *ms_out, int64_t c
  * 2^24), MH_E_NOMEM, MH_E_DEVICE. */
 mh_status mh_probe_mfma_i8(mh_ctx *ctx, int32_t iters, double *pops, hipStream_t stream);
 
+/* Sustained issue rate of the plain form's 96-bit multiply-accumulate (the
+ * v_mad_u64_u32 + v_addc_co_u32 pair of the plain kernel, one shared
+ * helper): eight workgroups of 256 threads per compute unit, sixteen
+ * independent accumulators per lane, `iters` rounds each, no memory traffic
+ * in the loop; one untimed launch, then the timed one (HIP events on
+ * `stream`).  *macs receives multiply-accumulates per second: the ceiling
+ * the plain kernel's VALU-bound loop can approach.  Synchronises `stream`;
+ * allocates and frees a small device buffer.
+ * Errors: MH_E_INVALID (ctx or macs null; iters below 1 or above 2^24),
+ * MH_E_NOMEM, MH_E_DEVICE. */
+mh_status mh_probe_valu_mac(mh_ctx *ctx, int32_t iters, double *macs, hipStream_t stream);
+
 /* Autotuning of the limb kernels' configuration (workgroup and wave tile,
  * pipeline depth, LDS sharing) per shape bucket: single products by limbs,
  * T and ceil(log2) of m, k, n; batches by limbs, T and ceil(log2) of their

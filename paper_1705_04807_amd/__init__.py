@@ -59,6 +59,7 @@ EXPORTS = (
     "mh_plan_gemm_tasks", "mh_ctx_set_autotune", "mh_ctx_tune_lookup", "mh_ctx_tune_cache_save",
     "mh_ctx_tune_cache_load", "mh_parent_size", "mh_layout_from_cartesian_padded",
     "mh_layout_to_cartesian_padded", "mh_ctx_kernel_times", "mh_probe_mfma_i8",
+    "mh_probe_valu_mac",
 )
 
 
@@ -109,6 +110,7 @@ def _load():
         "mh_ctx_kernel_times": ([P, ct.c_int, ct.POINTER(ct.c_double), I64, ct.POINTER(I64)],
                                 ct.c_int),
         "mh_probe_mfma_i8": ([P, I32, ct.POINTER(ct.c_double), P], ct.c_int),
+        "mh_probe_valu_mac": ([P, I32, ct.POINTER(ct.c_double), P], ct.c_int),
         "mh_ctx_set_autotune": ([P, ct.c_int], ct.c_int),
         "mh_ctx_tune_lookup": ([P, U32, I32, I64, I64, I64, ct.POINTER(I32)], ct.c_int),
         "mh_ctx_tune_cache_save": ([P, ct.c_char_p], ct.c_int),
@@ -182,6 +184,14 @@ def mh_probe_mfma_i8(ctx: int, iters: int, stream: int) -> float:
     pops = ct.c_double()
     check(lib.mh_probe_mfma_i8(ctx, iters, ct.byref(pops), stream), "mh_probe_mfma_i8")
     return pops.value
+
+
+def mh_probe_valu_mac(ctx: int, iters: int, stream: int) -> float:
+    """Sustained 96-bit multiply-accumulates per second of the plain form's
+    instruction pair (see include/mh.h)."""
+    macs = ct.c_double()
+    check(lib.mh_probe_valu_mac(ctx, iters, ct.byref(macs), stream), "mh_probe_valu_mac")
+    return macs.value
 
 
 def mh_ctx_kernel_times(ctx: int, kernel: int, cap: int = 4096) -> list[float]:

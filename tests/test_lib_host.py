@@ -34,7 +34,8 @@ def test_null_context_is_rejected():
                  lambda: mh.lib.mh_ctx_set_timing(None, 1),
                  lambda: mh.lib.mh_ctx_set_autotune(None, 1),
                  lambda: mh.lib.mh_ctx_destroy(None),
-                 lambda: mh.lib.mh_probe_mfma_i8(None, 1000, None, None)):
+                 lambda: mh.lib.mh_probe_mfma_i8(None, 1000, None, None),
+                 lambda: mh.lib.mh_probe_valu_mac(None, 1000, None, None)):
         assert call() == mh.MH_E_INVALID
 
 
