@@ -222,8 +222,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X and has no "
-              "multi-GPU path; run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on a single MI355X and has "
+              "no multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == BATCHED:
