@@ -283,9 +283,11 @@ typedef struct {
  * recursion level are independent).  descs is a host array.  No C block may
  * overlap another C block or any A or B block of the batch (MH_E_ALIAS); A
  * and B blocks may be shared.  The launch sequence (counter reset,
- * persistent packing kernel, persistent GEMM kernel) is captured once into a
- * HIP graph per context and replayed; only the queue contents change
- * between calls, through one host-to-device copy on `stream`.  Consecutive
+ * persistent packing kernels for the A and the B blocks, persistent GEMM
+ * kernel, whose workgroups serve the products of their own XCD's group
+ * first) is captured once into a HIP graph per context and replayed; only
+ * the queue contents change between calls, through one host-to-device copy
+ * on `stream`.  Consecutive
  * batched calls of one context must be ordered (same stream or
  * synchronised), since they share the queue and the workspace.  mode:
  * MH_MODE_AUTO and MH_MODE_LIMB_I8 run the limb form; the other forms run the
