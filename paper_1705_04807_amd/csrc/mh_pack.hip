@@ -198,35 +198,40 @@ __global__ __launch_bounds__(256) void k_pack_limb(int8_t *__restrict__ dst, int
 // forward search over the per-operand prefix sums finds the operand of a
 // run's first chunk, and the following chunks step forward from it.
 // Barriers between chunks (and after reading the popped index) order the
-// reuse of the LDS tile.  One instance per direction keeps the register
-// count, and so the number of resident workgroups, of the single-operand
-// kernel.
+// reuse of the LDS tile.  One instance per direction, the popped index read
+// as a scalar, and the queue arrays as separate read-only parameters (so
+// that a task's fields load into scalar registers) keep the register count,
+// and so the number of resident workgroups, of the single-operand kernel.
 template <int L, bool TRANS>
-__global__ __launch_bounds__(256) void k_pack_limb_batched(QueueView q, uint64_t *counter)
+__global__ __launch_bounds__(256) void k_pack_limb_batched(const BatchHeader *__restrict__ hdr,
+                                                           const PackTask *__restrict__ packs,
+                                                           const int64_t *__restrict__ pack_prefix,
+                                                           uint64_t *counter)
 {
     constexpr int64_t kGrab = 8;  // chunks per pop: one atomic and one search per 8 chunks
     __shared__ uint32_t tile[kChunk * kLdsStride];
-    __shared__ int64_t chunk_s;
-    const int64_t ncalls = q.hdr->ncalls;
+    __shared__ uint32_t chunk_s;
+    const int64_t ncalls = hdr->ncalls;
     const int64_t first = TRANS ? ncalls : 0, last = TRANS ? 2 * ncalls : ncalls;  // tasks
-    const int64_t base = q.pack_prefix[first], total = q.pack_prefix[last];        // chunks
-    const uint32_t p = q.hdr->p;
+    const int64_t base = pack_prefix[first], total = pack_prefix[last];            // chunks
+    const uint32_t p = hdr->p;
     const int32_t H = int32_t(limb_threshold(L));
     int64_t lo = first;
     for (;;) {
+        // (chunk counts stay below 2^31: a batch has fewer chunks)
         if (threadIdx.x == 0)
-            chunk_s = base + int64_t(atomicAdd((unsigned long long *)counter,
-                                               (unsigned long long)kGrab));
+            chunk_s = uint32_t(atomicAdd((unsigned long long *)counter,
+                                         (unsigned long long)kGrab));
         __syncthreads();
-        const int64_t c0 = chunk_s;
+        const int64_t c0 = base + int64_t(__builtin_amdgcn_readfirstlane(chunk_s));
         __syncthreads();
         if (c0 >= total) break;
-        lo = find_from(q.pack_prefix, last, lo, c0);
+        lo = find_from(pack_prefix, last, lo, c0);
         const int64_t c1 = c0 + kGrab < total ? c0 + kGrab : total;
         for (int64_t c = c0; c < c1; ++c) {
-            while (q.pack_prefix[lo + 1] <= c) ++lo;  // the next chunks may start the next operand
-            const PackTask t = q.packs[lo];
-            const int64_t local = c - q.pack_prefix[lo];
+            while (pack_prefix[lo + 1] <= c) ++lo;  // the next chunks may start the next operand
+            const PackTask t = packs[lo];
+            const int64_t local = c - pack_prefix[lo];
             const int64_t kchunks = (t.nkb + 1) / 2;
             const int64_t rho0 = (local / kchunks) * kChunk, kap0 = (local % kchunks) * kChunk;
             if (c > c0) __syncthreads();  // the previous chunk's LDS reads are done
@@ -278,8 +283,8 @@ hipError_t launch_pack_limb_batched(int L, const QueueView &q, uint64_t *counter
                     hipSuccess ||
                 per_cu < 1)
                 per_cu = 1;
-            hipLaunchKernelGGL(kern, dim3(unsigned(num_cu * per_cu)), dim3(256), 0, s, q,
-                               counters + i++);
+            hipLaunchKernelGGL(kern, dim3(unsigned(num_cu * per_cu)), dim3(256), 0, s, q.hdr,
+                               q.packs, q.pack_prefix, counters + i++);
             if ((e = hipGetLastError()) != hipSuccess) break;
         }
         return e;
