@@ -345,8 +345,13 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
     }
 }
 
+// At L >= 3 the four-wave 32 x 32 LDS configuration asks for two waves per
+// SIMD (it then fits 217 registers without spilling), so that two of its
+// workgroups, each with its own stage barrier, share a compute unit.
 template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF>
-__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_gemm_limb(LimbArgs a)
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N,
+                             (LDS && WAVES_M * WAVES_N == 4 && WM * WN == 1 && L >= 3) ? 2 : 1) void
+k_gemm_limb(LimbArgs a)
 {
     int64_t gm, gn;
     tile_of(blockIdx.x, a.grid_m, a.grid_n, 8, gm, gn);
@@ -579,9 +584,11 @@ bool limb_cfg_fits(int L, int idx)
 int limb_cfg_default(int L, int64_t m, int64_t n, int64_t k)
 {
     (void)k;
-    (void)L;
     if (m * n <= int64_t(512) * 512) return 6;  // 64 x 64 output blocks
-    return 11;                                 // 64 x 128, 8 waves sharing LDS stages
+    // 64 x 128, 8 waves sharing LDS stages; at L >= 3, 64 x 64 blocks of 4
+    // waves held to two waves per SIMD, so that two workgroups (each with
+    // its own barrier) share a compute unit
+    return L <= 2 ? 11 : 9;
 }
 
 hipError_t launch_gemm_limb_batched(int cfg, int L, const QueueView &q, uint64_t *counters,
