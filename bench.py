@@ -54,6 +54,11 @@ WORKLOADS = {
     # 8192^3 aligned product at the large prime: four 8-bit limbs, one k-block
     "modp_8192cube_p2^31-1_T64": dict(N=8192, T=64, p=P31, m=8192, k=8192, n=8192,
                                       off=(0, 0, 0, 0, 0, 0), seeds=(4001, 4002, 4003)),
+    # one GPU's share of the 8192^3 product split 4 x 2 over eight GPUs: the
+    # 2048 x 4096 block of C at (2048, 4096), all of k (no exchange needed)
+    "modp_8192cube_shard_2048x4096_p2^31-1_T64": dict(
+        N=8192, T=64, p=P31, m=2048, k=8192, n=4096,
+        off=(2048, 4096, 2048, 0, 0, 4096), seeds=(4001, 4002, 4003)),
     # 4096^3 aligned product at p = 65521: two limbs
     "modp_4096cube_p65521_T64": dict(N=4096, T=64, p=65521, m=4096, k=4096, n=4096,
                                      off=(0, 0, 0, 0, 0, 0), seeds=(2001, 2002, 2003)),

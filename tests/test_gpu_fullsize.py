@@ -2,8 +2,9 @@
 
 * 4096^3, p = 65521: every output of the limb and FP64 forms against the full
   oracle product.
-* 8192^3, p = 2^31 - 1 and the non-aligned 6000 x 3000 x 5000 product inside
-  8192^2 parents: the limb and plain forms (and the FP64 form where p < 2^26)
+* 8192^3, p = 2^31 - 1, one GPU's 2048 x 4096 x 8192 share of it (the 4 x 2
+  split of C), and the non-aligned 6000 x 3000 x 5000 product inside 8192^2
+  parents: the limb and plain forms (and the FP64 form where p < 2^26)
   must agree on every word; sampled
   outputs are recomputed one by one by the oracle; Freivalds' check (two
   random vectors) covers the whole block; words outside the C block are
@@ -111,6 +112,11 @@ def _check_block(mh, ctx, N, T, p, off, m, k, n, seeds, samples=384):
 
 def test_8192_cube_p31(mh, ctx):
     _check_block(mh, ctx, 8192, 64, P31, (0,) * 6, 8192, 8192, 8192, (4001, 4002, 4003))
+
+
+def test_8192_cube_shard_p31(mh, ctx):
+    _check_block(mh, ctx, 8192, 64, P31, (2048, 4096, 2048, 0, 0, 4096), 2048, 8192, 4096,
+                 (4001, 4002, 4003))
 
 
 def test_nonaligned_blocks_8192_parents(mh, ctx):
