@@ -33,6 +33,18 @@
  *  - A context is used by one host thread at a time.  It owns all device
  *    workspace (limb panels, task queues, captured graphs); nothing the
  *    library allocates is visible to the caller.
+ *  - The products of one context are ordered among themselves even when
+ *    they are issued on different streams: a product on another stream than
+ *    the context's previous one first makes its stream wait (on the device,
+ *    not the host) for that previous product, since both use the context's
+ *    workspace.  Products on different contexts are independent.  When the
+ *    workspace grows, the host waits for the context's own earlier work
+ *    only, never for the whole device.
+ *  - Workspace limit: a product whose operand panels would exceed the
+ *    context's limit (mh_ctx_set_workspace_limit; by default 1/8 of the
+ *    device memory) is run as consecutive sub-products over chunks of its
+ *    depth, then of its output rows and columns, accumulated into C in
+ *    turn; the result is the same.
  *  - No C++ exception crosses this interface.
  *  - Two environment variables override the limb form's choices, for
  *    tuning and testing: MH_LIMB_CFG=<index> forces a kernel configuration
@@ -125,6 +137,17 @@ const char *mh_status_string(mh_status s);
 /* First asynchronous HIP error seen by the context since the last call
  * (sticky until read, then cleared).  Queries the device without blocking. */
 mh_status mh_ctx_last_device_error(mh_ctx *ctx);
+
+/* Largest device workspace (bytes) one call of the context may hold for its
+ * operand panels: products (and batches) that would need more are split into
+ * sub-products that fit, as described above.  0 = no limit; otherwise at
+ * least 1 MiB (else MH_E_INVALID).  A held workspace above a new limit is
+ * released after the context's pending work (host wait on that work only). */
+mh_status mh_ctx_set_workspace_limit(mh_ctx *ctx, uint64_t bytes);
+
+/* The context's workspace limit (0 = none) and the bytes it holds now; either
+ * pointer may be null. */
+mh_status mh_ctx_workspace_info(mh_ctx *ctx, uint64_t *limit, uint64_t *held);
 
 /* Enable (1) or disable (0) timing: when on, every library kernel launch is
  * bracketed by HIP events recorded on the stream it is launched on. */
@@ -287,9 +310,11 @@ typedef struct {
  * kernel, whose workgroups serve the products of their own XCD's group
  * first) is captured once into a HIP graph per context and replayed; only
  * the queue contents change between calls, through one host-to-device copy
- * on `stream`.  Consecutive
- * batched calls of one context must be ordered (same stream or
- * synchronised), since they share the queue and the workspace.  mode:
+ * on `stream`; a graph is kept per kernel configuration and limb count, so
+ * batches of different shapes or moduli do not re-capture each other's.  Like
+ * every product of the context, a batch is ordered after the context's
+ * previous call, also across streams.  Products whose panels together exceed
+ * the workspace limit go out as several consecutive graphs.  mode:
  * MH_MODE_AUTO and MH_MODE_LIMB_I8 run the limb form; the other forms run the
  * products one after another with their own kernels.
  */

@@ -59,7 +59,7 @@ EXPORTS = (
     "mh_plan_gemm_tasks", "mh_ctx_set_autotune", "mh_ctx_tune_lookup", "mh_ctx_tune_cache_save",
     "mh_ctx_tune_cache_load", "mh_parent_size", "mh_layout_from_cartesian_padded",
     "mh_layout_to_cartesian_padded", "mh_ctx_kernel_times", "mh_probe_mfma_i8",
-    "mh_probe_valu_mac",
+    "mh_probe_valu_mac", "mh_ctx_set_workspace_limit", "mh_ctx_workspace_info",
 )
 
 
@@ -105,6 +105,8 @@ def _load():
         "mh_status_string": ([ct.c_int], ct.c_char_p),
         "mh_ctx_last_device_error": ([P], ct.c_int),
         "mh_ctx_set_timing": ([P, ct.c_int], ct.c_int),
+        "mh_ctx_set_workspace_limit": ([P, U64], ct.c_int),
+        "mh_ctx_workspace_info": ([P, ct.POINTER(U64), ct.POINTER(U64)], ct.c_int),
         "mh_ctx_kernel_time": ([P, ct.c_int, ct.POINTER(ct.c_double), ct.POINTER(I64), ct.c_int],
                                ct.c_int),
         "mh_ctx_kernel_times": ([P, ct.c_int, ct.POINTER(ct.c_double), I64, ct.POINTER(I64)],
@@ -164,6 +166,17 @@ def mh_status_string(status: int) -> str:
 
 def mh_ctx_last_device_error(ctx: int) -> int:
     return lib.mh_ctx_last_device_error(ctx)
+
+
+def mh_ctx_set_workspace_limit(ctx: int, nbytes: int) -> int:
+    return lib.mh_ctx_set_workspace_limit(ctx, nbytes)
+
+
+def mh_ctx_workspace_info(ctx: int) -> tuple[int, int, int]:
+    """Returns (status, limit in bytes (0 = none), bytes held)."""
+    lim, held = ct.c_uint64(), ct.c_uint64()
+    s = lib.mh_ctx_workspace_info(ctx, ct.byref(lim), ct.byref(held))
+    return s, lim.value, held.value
 
 
 def mh_ctx_set_timing(ctx: int, enable: bool) -> int:

@@ -32,6 +32,15 @@ __global__ void k_reset_counters(uint64_t *c)
     if (threadIdx.x < kBatchCounters) c[threadIdx.x] = 0;
 }
 
+void release_graphs(BatchedState &b)
+{
+    for (auto &g : b.graphs) {
+        if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+        if (g.second.graph) (void)hipGraphDestroy(g.second.graph);
+    }
+    b.graphs.clear();
+}
+
 int batch_cfg(int L, const std::vector<Plan> &plans)
 {
     double area = 0.0;
@@ -57,11 +66,11 @@ mh_status ensure_queue(mh_ctx *ctx, int64_t ncalls)
     if (b.queue_dev && ncalls <= b.queue_cap) return MH_OK;
     int64_t cap = 64;
     while (cap < ncalls) cap *= 2;
-    (void)hipDeviceSynchronize();
-    if (b.exec) (void)hipGraphExecDestroy(b.exec);
-    if (b.graph) (void)hipGraphDestroy(b.graph);
-    b.exec = nullptr;
-    b.graph = nullptr;
+    // The captured graphs read the old queue: wait for the context's
+    // launches to finish before destroying them and freeing it.
+    mh_status st = drain(ctx);
+    if (st != MH_OK) return st;
+    release_graphs(b);
     if (b.queue_dev) (void)hipFree(b.queue_dev);
     if (b.queue_host) (void)hipHostFree(b.queue_host);
     b.queue_dev = b.queue_host = nullptr;
@@ -94,24 +103,21 @@ mh_status ensure_queue(mh_ctx *ctx, int64_t ncalls)
         return MH_E_DEVICE;
     }
     b.queue_cap = cap;
-    b.graph_key = -1;
     return MH_OK;
 }
 
-// Capture reset -> pack -> GEMM for kernel configuration cfg and L limbs.
-mh_status ensure_graph(mh_ctx *ctx, int cfg, int L)
+// Capture reset -> pack -> GEMM for kernel configuration cfg and L limbs,
+// once per context, queue buffer and (cfg, L); returns the executable graph.
+hipGraphExec_t ensure_graph(mh_ctx *ctx, int cfg, int L)
 {
     BatchedState &b = ctx->batched;
     const int key = cfg * 8 + L;
-    if (b.exec && b.graph_key == key) return MH_OK;
-    if (b.exec) (void)hipGraphExecDestroy(b.exec);
-    if (b.graph) (void)hipGraphDestroy(b.graph);
-    b.exec = nullptr;
-    b.graph = nullptr;
+    auto it = b.graphs.find(key);
+    if (it != b.graphs.end()) return it->second.exec;
     const QueueView q = queue_view(b.queue_dev, b.queue_cap);
     hipStream_t cs = b.capture_stream;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return MH_E_DEVICE;
+        return nullptr;
     hipError_t e1 = launch_reset_counters(b.counters, cs);
     hipError_t e2 = launch_pack_limb_batched(L, q, b.counters, ctx->num_cu, cs);
     hipError_t e3 = launch_gemm_limb_batched(cfg, L, q, b.counters + 2, ctx->num_cu, cs);
@@ -120,18 +126,16 @@ mh_status ensure_graph(mh_ctx *ctx, int cfg, int L)
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || !g) {
         if (g) (void)hipGraphDestroy(g);
         (void)hipGetLastError();
-        return MH_E_DEVICE;
+        return nullptr;
     }
     hipGraphExec_t ex = nullptr;
     if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
         (void)hipGraphDestroy(g);
         (void)hipGetLastError();
-        return MH_E_DEVICE;
+        return nullptr;
     }
-    b.graph = g;
-    b.exec = ex;
-    b.graph_key = key;
-    return MH_OK;
+    b.graphs[key] = BatchedState::Captured{g, ex};
+    return ex;
 }
 
 bool block_overlap(const uint32_t *X, int64_t NX, int64_t rx, int64_t cx, int64_t xr, int64_t xc,
@@ -164,8 +168,7 @@ hipError_t launch_reset_counters(uint64_t *counters, hipStream_t s)
 void batched_release(mh_ctx *ctx)
 {
     BatchedState &b = ctx->batched;
-    if (b.exec) (void)hipGraphExecDestroy(b.exec);
-    if (b.graph) (void)hipGraphDestroy(b.graph);
+    release_graphs(b);
     if (b.capture_stream) (void)hipStreamDestroy(b.capture_stream);
     if (b.queue_dev) (void)hipFree(b.queue_dev);
     if (b.queue_host) (void)hipHostFree(b.queue_host);
@@ -286,15 +289,15 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
         first_call += group_calls[g];
     }
 
-    s = ensure_graph(ctx, cfg, L);
-    if (s != MH_OK) return s;
+    hipGraphExec_t exec = ensure_graph(ctx, cfg, L);
+    if (!exec) return MH_E_DEVICE;
     hipError_t e = hipMemcpyAsync(b.queue_dev, b.queue_host, queue_bytes(b.queue_cap),
                                   hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipEventRecord(b.staging_free, stream);
     if (e != hipSuccess) return note_error(ctx, e);
     TimedLaunch t;
     record_start(ctx, MH_K_BATCHED, stream, t);
-    e = hipGraphLaunch(b.exec, stream);
+    e = hipGraphLaunch(exec, stream);
     record_end(ctx, stream, t);
     return note_error(ctx, e);
 }
@@ -360,15 +363,13 @@ extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, in
     for (int32_t i = 0; i < count; ++i)
         if (prods[i].m > 0 && prods[i].n > 0 && prods[i].k > 0) live.push_back(i);
     if (live.empty()) return MH_OK;
+    CtxUse use(ctx, stream);
 
     if (mode != MH_MODE_AUTO && mode != MH_MODE_LIMB_I8) {
         // The plain, FP64 and elementwise forms have no batched kernel:
         // products run one after another.
         for (int32_t i : live) {
-            Plan pl;
-            plan_product(prods[i], mode, pl);
-            pl.sub = sub;
-            mh_status s = run_plain(ctx, pl, stream);
+            mh_status s = run_product(ctx, prods[i], mode, sub, WsSource{}, stream);
             if (s != MH_OK) return s;
         }
         return MH_OK;
@@ -377,15 +378,44 @@ extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, in
     const int L = limbs_for(p);
     std::vector<Plan> plans(live.size());
     for (size_t q = 0; q < live.size(); ++q) plan_product(prods[live[q]], MH_MODE_LIMB_I8, plans[q]);
+    const size_t cap = ctx->ws_limit ? ctx->ws_limit : SIZE_MAX;
+    size_t total = 0;
+    for (const Plan &pl : plans) total += plan_ws_bytes(pl);
     int cfg = -1;
     if (ctx->autotune) {
         cfg = tune_get(ctx, tune_key_batch(L, T, plans));
-        if (cfg < 0 && ctx->autotune == 2) cfg = tune_batch(ctx, plans, L, p, stream);
+        if (cfg < 0 && ctx->autotune == 2 && total <= cap) cfg = tune_batch(ctx, plans, L, p, stream);
     }
     if (!limb_cfg_fits(L, cfg)) cfg = batch_cfg(L, plans);  // none cached, or unusable for L
     for (size_t q = 0; q < live.size(); ++q) {
         plan_product(prods[live[q]], MH_MODE_LIMB_I8, plans[q], cfg);
         plans[q].sub = sub;
     }
-    return launch_batch(ctx, plans, cfg, L, p, stream, nullptr);
+    // Within the workspace limit: consecutive runs of products whose panels
+    // fit together go out as one batched graph each; a product whose own
+    // panels exceed the limit runs alone in chunks (run_product).
+    std::vector<Plan> part;
+    size_t part_bytes = 0;
+    auto flush_part = [&]() -> mh_status {
+        if (part.empty()) return MH_OK;
+        mh_status s = launch_batch(ctx, part, cfg, L, p, stream, nullptr);
+        part.clear();
+        part_bytes = 0;
+        return s;
+    };
+    for (size_t q = 0; q < plans.size(); ++q) {
+        const size_t need = plan_ws_bytes(plans[q]);
+        if (need > cap) {
+            mh_status s = run_product(ctx, prods[live[q]], MH_MODE_LIMB_I8, sub, WsSource{}, stream);
+            if (s != MH_OK) return s;
+            continue;
+        }
+        if (part_bytes + need > cap) {
+            mh_status s = flush_part();
+            if (s != MH_OK) return s;
+        }
+        part.push_back(plans[q]);
+        part_bytes += need;
+    }
+    return flush_part();
 }

@@ -25,9 +25,16 @@ struct BatchedState {
     hipEvent_t staging_free = nullptr;  // recorded after the last host-to-device queue copy
     uint64_t *counters = nullptr;       // device work counters (pack, GEMM)
     hipStream_t capture_stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int graph_key = -1;                 // kernel configuration the graph was captured for
+    // One captured graph per (kernel configuration, limbs): a batch whose
+    // configuration differs from the previous one's replays its own graph, so
+    // no graph is destroyed while a launch of it may still run.  All of them
+    // embed the queue's address and are destroyed together when the queue
+    // is reallocated (after the context's work has drained).
+    struct Captured {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::map<int, Captured> graphs;
 };
 
 struct DeviceGuard {
@@ -37,13 +44,41 @@ struct DeviceGuard {
 };
 
 mh_status note_error(mh_ctx *ctx, hipError_t e);
+
+// Ordering of the calls of one context.  Every call that uses memory the
+// context owns (workspace panels, the batch queue, tuning scratch) runs
+// between use_begin and use_end on its stream: use_begin makes the stream
+// wait for the previous such call when that one ran on another stream, and
+// use_end records the context's last-use event there.  So the calls of a
+// context are ordered even across streams, and drain (a host wait on that
+// one event) covers all of the context's work without synchronising the
+// whole device.
+void use_begin(mh_ctx *ctx, hipStream_t s);
+void use_end(mh_ctx *ctx, hipStream_t s);
+mh_status drain(mh_ctx *ctx);
+struct CtxUse {
+    mh_ctx *ctx;
+    hipStream_t s;
+    CtxUse(mh_ctx *c, hipStream_t st) : ctx(c), s(st) { use_begin(ctx, s); }
+    ~CtxUse() { use_end(ctx, s); }
+};
 void record_start(mh_ctx *ctx, int kernel, hipStream_t s, TimedLaunch &t);
 void record_end(mh_ctx *ctx, hipStream_t s, TimedLaunch &t);
 void *workspace(mh_ctx *ctx, size_t bytes);
+// Device memory for a product's panels: the context's growing workspace
+// (fixed == nullptr), or a fixed buffer of `cap` bytes that is never grown.
+struct WsSource {
+    char *fixed = nullptr;
+    size_t cap = 0;  // bytes usable; for the context's workspace, its limit (0: none)
+};
+size_t plan_ws_bytes(const Plan &pl);
+char *ws_get(mh_ctx *ctx, const WsSource &src, size_t bytes);
+mh_status run_product(mh_ctx *ctx, const Product &pr, int form, bool sub, const WsSource &src,
+                      hipStream_t s);
 bool outputs_alias(const Product &x, const Product &y);
 void batched_release(mh_ctx *ctx);
-mh_status run_plain(mh_ctx *ctx, const Plan &pl, hipStream_t s);
-mh_status run_limb(mh_ctx *ctx, const Plan &pl, hipStream_t s);
+mh_status run_plain(mh_ctx *ctx, const Plan &pl, char *ws, hipStream_t s);
+mh_status run_limb(mh_ctx *ctx, const Plan &pl, char *ws, hipStream_t s);
 mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int L, uint32_t p,
                        hipStream_t stream, uint32_t *c_override);
 
@@ -74,4 +109,10 @@ struct mh_ctx {
     std::map<std::string, mh::TuneEntry> tune; // shape bucket -> configuration
     void *tune_scratch = nullptr;              // output parent for tuning runs
     size_t tune_scratch_size = 0;
+    size_t ws_limit = 0;                       // largest workspace (bytes) a call may hold; 0: none
+    hipEvent_t last_use = nullptr;             // see use_begin / use_end
+    hipStream_t last_stream = nullptr;
+    bool used = false;
+    bool in_call = false;                      // between use_begin and use_end
+    hipStream_t cur_stream = nullptr;          // the current call's stream
 };

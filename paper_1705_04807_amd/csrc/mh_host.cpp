@@ -86,19 +86,52 @@ void record_end(mh_ctx *ctx, hipStream_t s, TimedLaunch &t)
     ctx->records.push_back(t);
 }
 
+void use_begin(mh_ctx *ctx, hipStream_t s)
+{
+    if (ctx->used && ctx->last_use && ctx->last_stream != s)
+        (void)hipStreamWaitEvent(s, ctx->last_use, 0);
+    ctx->in_call = true;
+    ctx->cur_stream = s;
+}
+
+void use_end(mh_ctx *ctx, hipStream_t s)
+{
+    ctx->in_call = false;
+    if (ctx->last_use && hipEventRecord(ctx->last_use, s) == hipSuccess) {
+        ctx->last_stream = s;
+        ctx->used = true;
+    }
+}
+
+// Inside a call, the work this call has already enqueued counts too: the
+// event is recorded on the call's stream first (which waited for the
+// previous call in use_begin), so the wait covers both.
+mh_status drain(mh_ctx *ctx)
+{
+    if (!ctx->last_use) return MH_OK;
+    if (ctx->in_call && hipEventRecord(ctx->last_use, ctx->cur_stream) == hipSuccess) {
+        ctx->last_stream = ctx->cur_stream;
+        ctx->used = true;
+    }
+    if (!ctx->used) return MH_OK;
+    return note_error(ctx, hipEventSynchronize(ctx->last_use));
+}
+
 // Device workspace owned by the context, grown on demand.  Growing waits
-// for all work on the device (the old block may still be in use).
+// for the context's earlier work (the old block may still be in use by it);
+// the caller's current call has enqueued nothing into the old block yet.
 void *workspace(mh_ctx *ctx, size_t bytes)
 {
     if (bytes <= ctx->ws_size) return ctx->ws;
     if (ctx->ws) {
-        (void)hipDeviceSynchronize();
+        (void)drain(ctx);
         (void)hipFree(ctx->ws);
         ctx->ws = nullptr;
         ctx->ws_size = 0;
     }
     size_t want = bytes + bytes / 8 + (size_t(1) << 20);
     want = (want + 0xFFFFF) & ~size_t(0xFFFFF);
+    if (ctx->ws_limit && want > ctx->ws_limit) want = std::max(bytes, ctx->ws_limit);
     void *p = nullptr;
     if (hipMalloc(&p, want) != hipSuccess) {
         (void)hipGetLastError();
@@ -107,6 +140,12 @@ void *workspace(mh_ctx *ctx, size_t bytes)
     ctx->ws = p;
     ctx->ws_size = want;
     return p;
+}
+
+char *ws_get(mh_ctx *ctx, const WsSource &src, size_t bytes)
+{
+    if (src.fixed) return bytes <= src.cap ? src.fixed : nullptr;
+    return (char *)workspace(ctx, bytes);
 }
 
 }  // namespace mh
@@ -125,7 +164,15 @@ extern "C" mh_status mh_ctx_create(mh_ctx **out, int hip_device)
     c->device = hip_device;
     DeviceGuard g(hip_device);
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) {
+        c->num_cu = prop.multiProcessorCount;
+        c->ws_limit = prop.totalGlobalMem / 8;  // default workspace limit
+    }
+    if (hipEventCreateWithFlags(&c->last_use, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return MH_E_DEVICE;
+    }
     *out = c;
     return MH_OK;
 }
@@ -135,8 +182,9 @@ extern "C" mh_status mh_ctx_destroy(mh_ctx *ctx)
     if (!ctx) return MH_E_INVALID;
     {
         DeviceGuard g(ctx->device);
-        (void)hipDeviceSynchronize();
+        (void)drain(ctx);
         for (auto &r : ctx->records) {
+            if (r.b) (void)hipEventSynchronize(r.b);
             if (r.a) (void)hipEventDestroy(r.a);
             if (r.b) (void)hipEventDestroy(r.b);
         }
@@ -144,6 +192,7 @@ extern "C" mh_status mh_ctx_destroy(mh_ctx *ctx)
         batched_release(ctx);
         if (ctx->ws) (void)hipFree(ctx->ws);
         if (ctx->tune_scratch) (void)hipFree(ctx->tune_scratch);
+        if (ctx->last_use) (void)hipEventDestroy(ctx->last_use);
     }
     delete ctx;
     return MH_OK;
@@ -158,6 +207,31 @@ extern "C" mh_status mh_ctx_last_device_error(mh_ctx *ctx)
     mh_status s = ctx->sticky;
     ctx->sticky = MH_OK;
     return s;
+}
+
+extern "C" mh_status mh_ctx_set_workspace_limit(mh_ctx *ctx, uint64_t bytes)
+{
+    if (!ctx) return MH_E_INVALID;
+    if (bytes != 0 && bytes < (uint64_t(1) << 20)) return MH_E_INVALID;
+    ctx->ws_limit = size_t(bytes);
+    if (ctx->ws && ctx->ws_limit && ctx->ws_size > ctx->ws_limit) {
+        // a held block above the new limit is released once the context's work is done
+        DeviceGuard g(ctx->device);
+        mh_status st = drain(ctx);
+        if (st != MH_OK) return st;
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_size = 0;
+    }
+    return MH_OK;
+}
+
+extern "C" mh_status mh_ctx_workspace_info(mh_ctx *ctx, uint64_t *limit, uint64_t *held)
+{
+    if (!ctx) return MH_E_INVALID;
+    if (limit) *limit = ctx->ws_limit;
+    if (held) *held = ctx->ws_size;
+    return MH_OK;
 }
 
 extern "C" mh_status mh_ctx_set_timing(mh_ctx *ctx, int enable)
@@ -676,7 +750,23 @@ static uint64_t horner_bias(uint32_t p)
     return b;
 }
 
-mh_status run_plain(mh_ctx *ctx, const Plan &pl, hipStream_t s)
+// Device bytes of a plan's operand panels (0 when it reads A and B in place).
+size_t plan_ws_bytes(const Plan &pl)
+{
+    const Product &p = pl.pr;
+    if (p.m <= 0 || p.n <= 0 || p.k <= 0) return 0;
+    if (pl.mode == MH_MODE_LIMB_I8) {
+        const size_t per_row = size_t(pl.kpad) * size_t(pl.L);  // nkb * 32 * L
+        return align256(size_t(pl.prow) * per_row) + align256(size_t(pl.pcol) * per_row) + 256;
+    }
+    if (pl.mode == MH_MODE_PLAIN_ELEMENTWISE || pl.in_place) return 0;
+    const int64_t T = p.T;
+    const int64_t prow = (pl.prow + T - 1) / T * T, pcol = (pl.pcol + T - 1) / T * T;
+    return align256(size_t(prow) * size_t(pl.kpad) * 4) +
+           align256(size_t(pl.kpad) * size_t(pcol) * 4) + 256;
+}
+
+mh_status run_plain(mh_ctx *ctx, const Plan &pl, char *ws, hipStream_t s)
 {
     const Product &p = pl.pr;
     const int64_t T = p.T;
@@ -720,11 +810,9 @@ mh_status run_plain(mh_ctx *ctx, const Plan &pl, hipStream_t s)
         // u32 panels, tile-major, of prow x kpad (A) and kpad x pcol (B).
         int64_t prow = (pl.prow + T - 1) / T * T, pcol = (pl.pcol + T - 1) / T * T;
         size_t abytes = size_t(prow) * size_t(pl.kpad) * 4;
-        size_t bbytes = size_t(pl.kpad) * size_t(pcol) * 4;
-        char *ws = (char *)workspace(ctx, abytes + bbytes + 256);
         if (!ws) return MH_E_NOMEM;
         uint32_t *Ap = (uint32_t *)ws;
-        uint32_t *Bp = (uint32_t *)(ws + ((abytes + 255) & ~size_t(255)));
+        uint32_t *Bp = (uint32_t *)(ws + align256(abytes));
         TimedLaunch t;
         record_start(ctx, MH_K_PACK, s, t);
         // A panel (rho, kap) <- A(ra - sr + rho, ca + kap) for rho in [sr, sr+m), kap < k
@@ -750,17 +838,15 @@ mh_status run_plain(mh_ctx *ctx, const Plan &pl, hipStream_t s)
     return note_error(ctx, e);
 }
 
-mh_status run_limb(mh_ctx *ctx, const Plan &pl, hipStream_t s)
+mh_status run_limb(mh_ctx *ctx, const Plan &pl, char *ws, hipStream_t s)
 {
     const Product &p = pl.pr;
     const int L = pl.L;
     const int64_t nkb = pl.kpad / 32;
     size_t abytes = size_t(pl.prow) * size_t(nkb) * 32 * L;
-    size_t bbytes = size_t(pl.pcol) * size_t(nkb) * 32 * L;
-    char *ws = (char *)workspace(ctx, abytes + bbytes + 512);
     if (!ws) return MH_E_NOMEM;
     int8_t *Ap = (int8_t *)ws;
-    int8_t *Bp = (int8_t *)(ws + ((abytes + 255) & ~size_t(255)));
+    int8_t *Bp = (int8_t *)(ws + align256(abytes));
     TimedLaunch t;
     record_start(ctx, MH_K_PACK, s, t);
     hipError_t e = launch_pack_limb(Ap, pl.prow, nkb, p.A, p.ra, p.ca, pl.sr, p.m, p.k, 0, 0,
@@ -797,6 +883,111 @@ mh_status run_limb(mh_ctx *ctx, const Plan &pl, hipStream_t s)
     return note_error(ctx, e);
 }
 
+// Plan of one product, with the tuner's configuration where it has one.
+// Timing runs of the tuner (mode 2) only when the caller lets the library
+// allocate (they write a scratch output parent).
+static void plan_tuned(mh_ctx *ctx, const Product &pr, int form, bool sub, bool may_tune,
+                       hipStream_t s, Plan &pl)
+{
+    plan_product(pr, form, pl);
+    if (pl.mode == MH_MODE_LIMB_I8 && ctx->autotune) {
+        int cfg = tune_get(ctx, tune_key_single(pl.L, pr));
+        if (cfg < 0 && ctx->autotune == 2 && may_tune) cfg = tune_single(ctx, pr, s);
+        if (cfg >= 0) plan_product(pr, MH_MODE_LIMB_I8, pl, cfg);
+    }
+    pl.sub = sub;
+}
+
+static mh_status run_plan(mh_ctx *ctx, const Plan &pl, const WsSource &src, hipStream_t s)
+{
+    const size_t need = plan_ws_bytes(pl);
+    char *ws = need ? ws_get(ctx, src, need) : nullptr;
+    if (need && !ws) return MH_E_NOMEM;
+    return pl.mode == MH_MODE_LIMB_I8 ? run_limb(ctx, pl, ws, s) : run_plain(ctx, pl, ws, s);
+}
+
+// Sub-product of pr: rows [i0, i0+mi), inner [l0, l0+kl), columns [j0, j0+nj)
+// in product coordinates.
+static Product sub_product(const Product &pr, int64_t i0, int64_t mi, int64_t l0, int64_t kl,
+                           int64_t j0, int64_t nj)
+{
+    Product q = pr;
+    q.rc = pr.rc + i0;
+    q.ra = pr.ra + i0;
+    q.cc = pr.cc + j0;
+    q.cb = pr.cb + j0;
+    q.ca = pr.ca + l0;
+    q.rb = pr.rb + l0;
+    q.m = mi;
+    q.k = kl;
+    q.n = nj;
+    return q;
+}
+
+// Chunk edges (mb, kc, nb) whose panels fit `cap` bytes.  Every chunk
+// boundary falls on a multiple of T in rows and columns and of max(64, T)
+// in depth, so each chunk has the panel shifts of the whole product and no
+// chunk needs more than the first.  Depth is split first (down to 1024),
+// then the longer of the two output edges (down to 1024), then depth to
+// its granule, then the output edges to T.  false if even that does not fit.
+static bool choose_chunks(const Product &pr, int form, size_t cap, int64_t &mb, int64_t &kc,
+                          int64_t &nb)
+{
+    const int64_t T = pr.T, kq = std::max<int64_t>(64, T);
+    auto up = [](int64_t x, int64_t q) { return (x + q - 1) / q * q; };
+    auto bytes = [&]() {
+        Plan pl;
+        plan_product(sub_product(pr, 0, std::min(mb, pr.m), 0, std::min(kc, pr.k), 0,
+                                 std::min(nb, pr.n)),
+                     form, pl);
+        return plan_ws_bytes(pl);
+    };
+    auto half_k = [&]() { kc = std::max(kq, up((kc + 1) / 2, kq)); };
+    auto half_mn = [&]() {
+        int64_t &x = mb >= nb ? mb : nb;
+        x = std::max(T, up((x + 1) / 2, T));
+    };
+    mb = pr.m;
+    kc = pr.k;
+    nb = pr.n;
+    while (bytes() > cap && kc > 1024) half_k();
+    while (bytes() > cap && std::max(mb, nb) > 1024) half_mn();
+    while (bytes() > cap && kc > kq) half_k();
+    while (bytes() > cap && std::max(mb, nb) > T) half_mn();
+    return bytes() <= cap;
+}
+
+mh_status run_product(mh_ctx *ctx, const Product &pr, int form, bool sub, const WsSource &src,
+                      hipStream_t s)
+{
+    if (pr.m == 0 || pr.n == 0 || pr.k == 0) return MH_OK;
+    Plan pl;
+    plan_tuned(ctx, pr, form, sub, !src.fixed, s, pl);
+    const size_t cap = src.fixed ? src.cap : (ctx->ws_limit ? ctx->ws_limit : SIZE_MAX);
+    if (plan_ws_bytes(pl) <= cap) return run_plan(ctx, pl, src, s);
+    // Too large for the workspace allowed: sub-products over chunks of the
+    // rows, the depth and the columns, each accumulated into C in turn
+    // (addition mod p is associative, so the result is the same; for the
+    // subtractive update every chunk subtracts its part).
+    form = pl.mode;  // the whole product's form, also for small trailing chunks
+    int64_t mb, kc, nb;
+    if (!choose_chunks(pr, form, cap, mb, kc, nb)) return MH_E_NOMEM;
+    for (int64_t i0 = 0; i0 < pr.m; i0 += mb)
+        for (int64_t j0 = 0; j0 < pr.n; j0 += nb)
+            for (int64_t l0 = 0; l0 < pr.k; l0 += kc) {
+                const Product q = sub_product(pr, i0, std::min(mb, pr.m - i0), l0,
+                                              std::min(kc, pr.k - l0), j0, std::min(nb, pr.n - j0));
+                Plan ql;
+                plan_tuned(ctx, q, form, sub, !src.fixed, s, ql);
+                if (plan_ws_bytes(ql) > cap) plan_product(q, form, ql);  // built-in tile
+                ql.sub = sub;
+                if (plan_ws_bytes(ql) > cap) return MH_E_NOMEM;
+                mh_status st = run_plan(ctx, ql, src, s);
+                if (st != MH_OK) return st;
+            }
+    return MH_OK;
+}
+
 }  // namespace mh
 
 extern "C" mh_status mh_matmul_modp(mh_ctx *ctx, uint32_t *C, int64_t NC, int64_t rc, int64_t cc,
@@ -814,16 +1005,7 @@ extern "C" mh_status mh_matmul_modp(mh_ctx *ctx, uint32_t *C, int64_t NC, int64_
     if (s == MH_OK) s = check_form_modulus(form, p);
     if (s != MH_OK) return s;
     if (m == 0 || n == 0 || k == 0) return MH_OK;
-    Plan pl;
-    plan_product(pr, form, pl);
-    pl.sub = sub;
     DeviceGuard g(ctx->device);
-    if (pl.mode != MH_MODE_LIMB_I8) return run_plain(ctx, pl, stream);
-    if (ctx->autotune) {
-        int cfg = tune_get(ctx, tune_key_single(pl.L, pr));
-        if (cfg < 0 && ctx->autotune == 2) cfg = tune_single(ctx, pr, stream);
-        if (cfg >= 0) plan_product(pr, MH_MODE_LIMB_I8, pl, cfg);
-        pl.sub = sub;
-    }
-    return run_limb(ctx, pl, stream);
+    CtxUse use(ctx, stream);
+    return run_product(ctx, pr, form, sub, WsSource{}, stream);
 }

@@ -51,7 +51,7 @@ uint32_t *tune_scratch(mh_ctx *ctx, int64_t N)
 {
     const size_t bytes = size_t(N) * size_t(N) * 4;
     if (bytes > ctx->tune_scratch_size) {
-        (void)hipDeviceSynchronize();
+        (void)drain(ctx);
         if (ctx->tune_scratch) (void)hipFree(ctx->tune_scratch);
         ctx->tune_scratch = nullptr;
         ctx->tune_scratch_size = 0;
@@ -133,7 +133,11 @@ int tune_single(mh_ctx *ctx, const Product &p, hipStream_t s)
         if (!limb_cfg_fits(L, cfg)) continue;
         Plan pl;
         plan_product(q, MH_MODE_LIMB_I8, pl, cfg);
-        const double ms = time_ms(s, [&] { return run_limb(ctx, pl, s); }, 2);
+        const size_t need = plan_ws_bytes(pl);
+        if (ctx->ws_limit && need > ctx->ws_limit) continue;  // would not run unchunked
+        char *ws = (char *)workspace(ctx, need);
+        if (!ws) continue;
+        const double ms = time_ms(s, [&] { return run_limb(ctx, pl, ws, s); }, 2);
         if (ms > 0.0 && (best < 0 || ms < best_ms)) {
             best = cfg;
             best_ms = ms;

@@ -4,11 +4,11 @@
   oracle product.
 * 8192^3, p = 2^31 - 1, one GPU's 2048 x 4096 x 8192 share of it (the 4 x 2
   split of C), and the non-aligned 6000 x 3000 x 5000 product inside 8192^2
-  parents: the limb and plain forms (and the FP64 form where p < 2^26)
-  must agree on every word; sampled
-  outputs are recomputed one by one by the oracle; Freivalds' check (two
-  random vectors) covers the whole block; words outside the C block are
-  unchanged.
+  parents: every word of the C parent against the oracle's full product
+  (the definition on the Cartesian parents, so words outside the block must
+  be unchanged); the limb and plain forms (and the FP64 form where
+  p < 2^26) agree on every word; sampled outputs recomputed one by one and
+  Freivalds' check (two random vectors) as second, independent checks.
 """
 
 import numpy as np
@@ -90,10 +90,13 @@ def _check_block(mh, ctx, N, T, p, off, m, k, n, seeds, samples=384):
         assert torch.equal(Cm, Cm3)
     got = host_of(to_cart(mh, ctx, Cm, N, T))
     A, B, C0 = (host_of(X) for X in cart)
-    # outside the block nothing moved
-    mask = np.ones((N, N), bool)
-    mask[rc:rc + m, cc:cc + n] = False
-    assert np.array_equal(got[mask], C0[mask])
+    # the whole parent against the oracle's full product, word by word
+    say("fullsize oracle", N, off, m, k, n, p)
+    want = C0.copy()
+    oracle.matmul_modp_view(want, A, B, p, rc, cc, ra, ca, rb, cb, m, k, n)
+    bad = int(np.count_nonzero(got != want))
+    assert bad == 0, "%d words differ from the oracle" % bad
+    del want
     Ab = np.ascontiguousarray(A[ra:ra + m, ca:ca + k])
     Bb = np.ascontiguousarray(B[rb:rb + k, cb:cb + n])
     Cb0 = np.ascontiguousarray(C0[rc:rc + m, cc:cc + n])

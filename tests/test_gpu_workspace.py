@@ -1,0 +1,158 @@
+"""Context workspace: the limit on operand panels, and ordering across streams.
+
+* A product whose full-depth panels exceed the context's workspace limit runs
+  as sub-products over chunks of the depth (and, under a tighter limit, of
+  the output rows and columns), accumulated into C: the result must still
+  equal the oracle's on every word, in the limb, plain and FP64 forms, for
+  the additive and the subtractive update, and the workspace the context
+  holds afterwards stays within the limit.
+* A batch whose panels together exceed the limit goes out as several graphs,
+  a product too large on its own in chunks.
+* Two products of one context issued on two different streams, with no
+  synchronisation between them, share the context's workspace: the second
+  must wait for the first on the device (both results against the oracle).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_util import (device_of, host_of, parent_host, say, stream_handle, to_cart,
+                            to_mh, torch_cuda)
+
+pytestmark = pytest.mark.gpu
+
+MiB = 1 << 20
+
+
+@pytest.fixture(scope="module")
+def mh():
+    import paper_1705_04807_amd as m
+    return m
+
+
+def _panel_bytes(mh, N, off, m, k, n, p, T, mode):
+    rc, cc, ra, ca, rb, cb = off
+    s, info = mh.mh_plan_describe(N, rc, cc, N, ra, ca, N, rb, cb, m, k, n, p, T, mode)
+    mh.check(s)
+    if info.mode == mh.MH_MODE_LIMB_I8:
+        kpad = (k + 63) // 64 * 64
+        rows = (off[0] % min(T, info.tile_m) + m + info.tile_m - 1) // info.tile_m * info.tile_m
+        cols = (off[1] % min(T, info.tile_n) + n + info.tile_n - 1) // info.tile_n * info.tile_n
+        return (rows + cols) * kpad * info.limbs
+    return None
+
+
+@pytest.mark.parametrize("case", [
+    # (p, T, N, offsets, m, k, n, mode, limit MiB)
+    (2**31 - 1, 64, 4096, (64, 33, 1000, 1500, 517, 2048), 2000, 2500, 1500, 2, 16),
+    (65521, 32, 4096, (3, 70, 1, 2, 5, 9), 3000, 1000, 3100, 2, 1),
+    (65521, 128, 2048, (128, 0, 0, 130, 7, 128), 1500, 1900, 1200, 2 | 0x100, 2),
+    ((1 << 24) - 3, 64, 2048, (17, 3, 100, 9, 200, 33), 1700, 1800, 1600, 1, 1),
+    (65521, 16, 2048, (5, 6, 7, 8, 9, 10), 1500, 1400, 1300, 3, 1),
+])
+def test_product_under_workspace_limit(mh, case):
+    torch = torch_cuda()
+    p, T, N, off, m, k, n, mode, lim = case
+    rc, cc, ra, ca, rb, cb = off
+    A, B, C = (parent_host(s, p, N) for s in (7001, 7002, 7003))
+    ctx = mh.mh_ctx_create(0)
+    try:
+        mh.check(mh.mh_ctx_set_workspace_limit(ctx, lim * MiB))
+        full = _panel_bytes(mh, N, off, m, k, n, p, T, mode & 0xFF)
+        if full is not None:
+            assert full > lim * MiB  # the whole product would not fit
+        Ad, Bd, Cd = (to_mh(mh, ctx, device_of(X), N, T) for X in (A, B, C))
+        say("ws limit", lim, "MiB", p, T, off, m, k, n, mode)
+        mh.check(mh.mh_matmul_modp(ctx, Cd.data_ptr(), N, rc, cc, Ad.data_ptr(), N, ra, ca,
+                                   Bd.data_ptr(), N, rb, cb, m, k, n, p, T, mode,
+                                   stream_handle()))
+        got = host_of(to_cart(mh, ctx, Cd, N, T))
+        want = C.copy()
+        oracle.matmul_modp_view(want, A, B, p, rc, cc, ra, ca, rb, cb, m, k, n,
+                                subtract=bool(mode & 0x100))
+        assert np.array_equal(got, want)
+        s, limit, held = mh.mh_ctx_workspace_info(ctx)
+        mh.check(s)
+        assert limit == lim * MiB and held <= limit
+        assert mh.mh_ctx_last_device_error(ctx) == 0
+    finally:
+        mh.mh_ctx_destroy(ctx)
+    torch.cuda.empty_cache()
+
+
+def test_batch_under_workspace_limit(mh):
+    p, T, N = 65521, 64, 2048
+    A, B = parent_host(7101, p, N), parent_host(7102, p, N)
+    Cs = [parent_host(7110 + j, p, N) for j in range(2)]
+    ctx = mh.mh_ctx_create(0)
+    try:
+        mh.check(mh.mh_ctx_set_workspace_limit(ctx, 4 * MiB))
+        Ad, Bd = to_mh(mh, ctx, device_of(A), N, T), to_mh(mh, ctx, device_of(B), N, T)
+        Cds = [to_mh(mh, ctx, device_of(C), N, T) for C in Cs]
+        g = np.random.default_rng(7100)
+        # one product whose own panels (about 2 x 1920 x 1920 x 2 bytes = 14 MiB)
+        # exceed the limit, in parent 1; twelve small ones on a 4 x 3 grid of
+        # disjoint cells in parent 0 (several graphs of a few products each)
+        kept = [dict(ci=1, rc=100, cc=100, m=1900, k=1900, n=1900, ra=3, ca=50, rb=70, cb=11)]
+        for i in range(12):
+            m, k, n = int(g.integers(100, 400)), int(g.integers(100, 900)), int(g.integers(100, 400))
+            kept.append(dict(ci=0, rc=(i % 4) * 500, cc=(i // 4) * 500, m=m, k=k, n=n,
+                             ra=int(g.integers(0, N - m + 1)), ca=int(g.integers(0, N - k + 1)),
+                             rb=int(g.integers(0, N - k + 1)), cb=int(g.integers(0, N - n + 1))))
+        descs = mh.make_descs([dict(C=Cds[c["ci"]].data_ptr(), A=Ad.data_ptr(),
+                                    B=Bd.data_ptr(), NC=N, NA=N, NB=N, rc=c["rc"], cc=c["cc"],
+                                    ra=c["ra"], ca=c["ca"], rb=c["rb"], cb=c["cb"], m=c["m"],
+                                    k=c["k"], n=c["n"]) for c in kept])
+        say("batch under ws limit", len(kept))
+        mh.check(mh.mh_matmul_modp_batched(ctx, descs, len(kept), p, T, mh.MH_MODE_LIMB_I8,
+                                           stream_handle()))
+        for c in kept:
+            oracle.matmul_modp_view(Cs[c["ci"]], A, B, p, c["rc"], c["cc"], c["ra"], c["ca"],
+                                    c["rb"], c["cb"], c["m"], c["k"], c["n"])
+        for j in range(2):
+            assert np.array_equal(host_of(to_cart(mh, ctx, Cds[j], N, T)), Cs[j]), j
+        s, limit, held = mh.mh_ctx_workspace_info(ctx)
+        assert held <= limit
+        assert mh.mh_ctx_last_device_error(ctx) == 0
+    finally:
+        mh.mh_ctx_destroy(ctx)
+
+
+def test_products_on_two_streams_share_workspace(mh):
+    torch = torch_cuda()
+    p, T, N = 65521, 64, 4096
+    A, B, C1, C2 = (parent_host(s, p, N) for s in (7201, 7202, 7203, 7204))
+    ctx = mh.mh_ctx_create(0)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    try:
+        Ad, Bd, D1, D2 = (to_mh(mh, ctx, device_of(X), N, T) for X in (A, B, C1, C2))
+        torch.cuda.synchronize()
+        say("two streams")
+        # a long product on s1, then at once a different one on s2: its packing
+        # would overwrite the panels the first one's GEMM still reads
+        mh.check(mh.mh_matmul_modp(ctx, D1.data_ptr(), N, 0, 0, Ad.data_ptr(), N, 0, 0,
+                                   Bd.data_ptr(), N, 0, 0, N, N, N, p, T, mh.MH_MODE_LIMB_I8,
+                                   s1.cuda_stream))
+        mh.check(mh.mh_matmul_modp(ctx, D2.data_ptr(), N, 64, 0, Bd.data_ptr(), N, 0, 64,
+                                   Ad.data_ptr(), N, 64, 0, 4000, 4000, 4000, p, T,
+                                   mh.MH_MODE_LIMB_I8, s2.cuda_stream))
+        # and a batch on s1 after that, then a single product on s2 again
+        d = mh.make_descs([dict(C=D1.data_ptr(), A=Ad.data_ptr(), B=Bd.data_ptr(), NC=N, NA=N,
+                                NB=N, rc=100, cc=200, ra=5, ca=6, rb=7, cb=8, m=1500, k=2000,
+                                n=1700)])
+        mh.check(mh.mh_matmul_modp_batched(ctx, d, 1, p, T, mh.MH_MODE_LIMB_I8, s1.cuda_stream))
+        mh.check(mh.mh_matmul_modp(ctx, D2.data_ptr(), N, 3, 5, Ad.data_ptr(), N, 0, 0,
+                                   Bd.data_ptr(), N, 0, 0, 3000, 3500, 2500, p, T,
+                                   mh.MH_MODE_LIMB_I8, s2.cuda_stream))
+        torch.cuda.synchronize()
+        want1, want2 = C1.copy(), C2.copy()
+        oracle.matmul_modp_view(want1, A, B, p, 0, 0, 0, 0, 0, 0, N, N, N)
+        oracle.matmul_modp_view(want2, B, A, p, 64, 0, 0, 64, 64, 0, 4000, 4000, 4000)
+        oracle.matmul_modp_view(want1, A, B, p, 100, 200, 5, 6, 7, 8, 1500, 2000, 1700)
+        oracle.matmul_modp_view(want2, A, B, p, 3, 5, 0, 0, 0, 0, 3000, 3500, 2500)
+        assert np.array_equal(host_of(to_cart(mh, ctx, D1, N, T)), want1)
+        assert np.array_equal(host_of(to_cart(mh, ctx, D2, N, T)), want2)
+        assert mh.mh_ctx_last_device_error(ctx) == 0
+    finally:
+        mh.mh_ctx_destroy(ctx)
