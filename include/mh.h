@@ -291,6 +291,32 @@ mh_status mh_matmul_modp(mh_ctx *ctx, uint32_t *C, int64_t NC, int64_t rc, int64
                          int64_t k, int64_t n, uint32_t p, int32_t T, int32_t mode,
                          hipStream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product, arguments, result and errors as mh_matmul_modp, but the operand
+ * panels live in a fixed 128 MiB device array of the library (one per GPU,
+ * held until the process ends) instead of the context's workspace, and the
+ * call makes no device allocation of any kind (no hipMalloc or hipFree, no
+ * autotuning runs -- configurations already in the context's tuning cache
+ * are used -- and no timing events even with timing on).  A product whose
+ * panels exceed 128 MiB runs as consecutive sub-products over chunks of its
+ * depth, then of its output rows and columns, each within the array; should
+ * even the smallest chunk not fit, the call returns MH_E_NOMEM before
+ * anything is enqueued for it.  The array's contents are left from the last
+ * call and never relied on (packing writes every panel byte it reads).
+ * Calls through one context are ordered as the context's other calls are;
+ * calls through different contexts (or host threads) on the same GPU share
+ * the one array and race if they may overlap on the device: the caller
+ * must order them (one stream, or events).  MH_E_DEVICE if the array's
+ * device address could not be obtained when the context was created.
+ */
+mh_status mh_matmul_modp_noalloc(mh_ctx *ctx, uint32_t *C, int64_t NC, int64_t rc, int64_t cc,
+                                 const uint32_t *A, int64_t NA, int64_t ra, int64_t ca,
+                                 const uint32_t *B, int64_t NB, int64_t rb, int64_t cb,
+                                 int64_t m, int64_t k, int64_t n, uint32_t p, int32_t T,
+                                 int32_t mode, hipStream_t stream);
+
 /* One independent product of a batch (same meaning as mh_matmul_modp). */
 typedef struct {
     uint32_t *C;

@@ -60,6 +60,7 @@ EXPORTS = (
     "mh_ctx_tune_cache_load", "mh_parent_size", "mh_layout_from_cartesian_padded",
     "mh_layout_to_cartesian_padded", "mh_ctx_kernel_times", "mh_probe_mfma_i8",
     "mh_probe_valu_mac", "mh_ctx_set_workspace_limit", "mh_ctx_workspace_info",
+    "mh_matmul_modp_noalloc",
 )
 
 
@@ -127,6 +128,8 @@ def _load():
         "mh_layout_to_cartesian_padded": ([P, P, I64, I64, I64, P, I64, I32, P], ct.c_int),
         "mh_matmul_modp": ([P, P, I64, I64, I64, P, I64, I64, I64, P, I64, I64, I64, I64, I64,
                             I64, U32, I32, I32, P], ct.c_int),
+        "mh_matmul_modp_noalloc": ([P, P, I64, I64, I64, P, I64, I64, I64, P, I64, I64, I64, I64,
+                                    I64, I64, U32, I32, I32, P], ct.c_int),
         "mh_matmul_modp_batched": ([P, ct.POINTER(mh_mm_desc), I32, U32, I32, I32, P], ct.c_int),
         "mh_plan_describe": ([I64] * 12 + [U32, I32, I32, ct.POINTER(mh_plan_info)], ct.c_int),
         "mh_plan_leaves": ([I64] * 12 + [I32, ct.POINTER(I64), I64, ct.POINTER(I64)], ct.c_int),
@@ -289,6 +292,13 @@ def mh_matmul_modp(ctx, C: int, NC: int, rc: int, cc: int, A: int, NA: int, ra: 
                    mode: int = MH_MODE_AUTO, stream: int = 0) -> int:
     return lib.mh_matmul_modp(ctx, C, NC, rc, cc, A, NA, ra, ca, B, NB, rb, cb, m, k, n, p, T,
                               mode, stream)
+
+
+def mh_matmul_modp_noalloc(ctx, C: int, NC: int, rc: int, cc: int, A: int, NA: int, ra: int,
+                           ca: int, B: int, NB: int, rb: int, cb: int, m: int, k: int, n: int,
+                           p: int, T: int, mode: int = MH_MODE_AUTO, stream: int = 0) -> int:
+    return lib.mh_matmul_modp_noalloc(ctx, C, NC, rc, cc, A, NA, ra, ca, B, NB, rb, cb, m, k, n,
+                                      p, T, mode, stream)
 
 
 def make_descs(items) -> ct.Array:

@@ -62,6 +62,13 @@ struct CtxUse {
     CtxUse(mh_ctx *c, hipStream_t st) : ctx(c), s(st) { use_begin(ctx, s); }
     ~CtxUse() { use_end(ctx, s); }
 };
+// Inside a call that must not allocate, timing is off (it would create HIP
+// events).
+struct NoTiming {
+    mh_ctx *ctx;
+    explicit NoTiming(mh_ctx *c);
+    ~NoTiming();
+};
 void record_start(mh_ctx *ctx, int kernel, hipStream_t s, TimedLaunch &t);
 void record_end(mh_ctx *ctx, hipStream_t s, TimedLaunch &t);
 void *workspace(mh_ctx *ctx, size_t bytes);
@@ -76,6 +83,15 @@ char *ws_get(mh_ctx *ctx, const WsSource &src, size_t bytes);
 mh_status run_product(mh_ctx *ctx, const Product &pr, int form, bool sub, const WsSource &src,
                       hipStream_t s);
 bool outputs_alias(const Product &x, const Product &y);
+Product make_product(uint32_t *C, int64_t NC, int64_t rc, int64_t cc, const uint32_t *A,
+                     int64_t NA, int64_t ra, int64_t ca, const uint32_t *B, int64_t NB,
+                     int64_t rb, int64_t cb, int64_t m, int64_t k, int64_t n, uint32_t p,
+                     int32_t T);
+// Panel scratch of the no-allocation entry point (mh_noalloc.hip): its size,
+// and its device address on `device` (looked up once per device with that
+// device current; nullptr if unavailable).
+size_t noalloc_scratch_bytes();
+void *noalloc_scratch_init(int device);
 void batched_release(mh_ctx *ctx);
 mh_status run_plain(mh_ctx *ctx, const Plan &pl, char *ws, hipStream_t s);
 mh_status run_limb(mh_ctx *ctx, const Plan &pl, char *ws, hipStream_t s);
@@ -115,4 +131,9 @@ struct mh_ctx {
     bool used = false;
     bool in_call = false;                      // between use_begin and use_end
     hipStream_t cur_stream = nullptr;          // the current call's stream
+    void *noalloc_ws = nullptr;                // device address of the no-allocation scratch
+    bool no_timing = false;                    // inside mh_matmul_modp_noalloc
 };
+
+inline mh::NoTiming::NoTiming(mh_ctx *c) : ctx(c) { ctx->no_timing = true; }
+inline mh::NoTiming::~NoTiming() { ctx->no_timing = false; }

@@ -73,7 +73,7 @@ void record_start(mh_ctx *ctx, int kernel, hipStream_t s, TimedLaunch &t)
 {
     t.kernel = kernel;
     t.a = t.b = nullptr;
-    if (!ctx->timing) return;
+    if (!ctx->timing || ctx->no_timing) return;
     t.a = take_event(ctx);
     t.b = take_event(ctx);
     if (t.a) (void)hipEventRecord(t.a, s);
@@ -81,7 +81,7 @@ void record_start(mh_ctx *ctx, int kernel, hipStream_t s, TimedLaunch &t)
 
 void record_end(mh_ctx *ctx, hipStream_t s, TimedLaunch &t)
 {
-    if (!ctx->timing || !t.a || !t.b) return;
+    if (!ctx->timing || ctx->no_timing || !t.a || !t.b) return;
     (void)hipEventRecord(t.b, s);
     ctx->records.push_back(t);
 }
@@ -173,6 +173,8 @@ extern "C" mh_status mh_ctx_create(mh_ctx **out, int hip_device)
         delete c;
         return MH_E_DEVICE;
     }
+    // the no-allocation entry point's panel scratch on this device
+    c->noalloc_ws = noalloc_scratch_init(hip_device);
     *out = c;
     return MH_OK;
 }
@@ -516,10 +518,10 @@ void plan_product(const Product &p, int mode, Plan &pl, int forced_cfg)
 
 // ------------------------------------------------------- planner queries
 
-static Product make_product(uint32_t *C, int64_t NC, int64_t rc, int64_t cc, const uint32_t *A,
-                            int64_t NA, int64_t ra, int64_t ca, const uint32_t *B, int64_t NB,
-                            int64_t rb, int64_t cb, int64_t m, int64_t k, int64_t n, uint32_t p,
-                            int32_t T)
+Product mh::make_product(uint32_t *C, int64_t NC, int64_t rc, int64_t cc, const uint32_t *A,
+                        int64_t NA, int64_t ra, int64_t ca, const uint32_t *B, int64_t NB,
+                        int64_t rb, int64_t cb, int64_t m, int64_t k, int64_t n, uint32_t p,
+                        int32_t T)
 {
     Product pr;
     pr.C = C;
