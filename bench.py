@@ -13,6 +13,12 @@ HBM in Morton-hybrid layout.  Prints one JSON line:
   fp64   = the FP64-MFMA form on the same workload, when p < 2^26;
   cpu_baseline = the CPU oracle (triple loop, 128-bit accumulators) on a
              bounded sample of output rows of the same workload.
+The default run (the 8192^3 product) adds one key per other workload of the
+metric, each with the same fields (value, ms_per_step, config, roofline,
+plain, fp64 where p < 2^26, cpu_baseline on a smaller sample), timed after
+the headline: aligned_4096cube_p65521, nonaligned_8192parents_p65521 and
+batched_512_tu_level_p65521 (the batched graph, a loop of single calls and
+the plain form's batch).  --no-extras leaves them out.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
        python bench.py --copy-calibration   (plain 1 GiB device copy, three times:
@@ -77,6 +83,11 @@ WORKLOADS = {
 # 512 uneven independent products of one TU recursion level, one batched call
 BATCHED = "batched_512_tu_level_8192parents_p65521_T64"
 DEFAULT = "modp_8192cube_p2^31-1_T64"
+# keys of the default line beside the headline: the other workloads of the metric
+EXTRA_SINGLE = (("aligned_4096cube_p65521", "modp_4096cube_p65521_T64"),
+                ("nonaligned_8192parents_p65521", "modp_nonaligned_8192parents_p65521_T64"))
+EXTRA_BATCHED = "batched_512_tu_level_p65521"
+INT8_UNIT = "TOP/s"  # int8 multiply-add operations (two per multiply-accumulate)
 
 
 def log(*a):
@@ -86,25 +97,16 @@ def log(*a):
 KERNEL_SOURCES = ("paper_1705_04807_amd/csrc/mh_gemm_limb.hip",
                   "paper_1705_04807_amd/csrc/mh_device.h",
                   "paper_1705_04807_amd/csrc/mh_internal.h")
+BATCHED_SOURCES = KERNEL_SOURCES + ("paper_1705_04807_amd/csrc/mh_pack.hip",
+                                    "paper_1705_04807_amd/csrc/mh_batched.hip")
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(files=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
-
-
-def sustained_int8(mh, ctx, stream, args):
-    """The device's sustained int8 MFMA rate (T ops/s) from mh_probe_mfma_i8,
-    run after the timed region: the best of three calls (the clock takes a
-    few milliseconds to settle under the load); None with --no-probe."""
-    if args.no_probe:
-        return None
-    log("sustained int8 MFMA probe")
-    return max(mh.mh_probe_mfma_i8(ctx, PROBE_ITERS, stream.cuda_stream)
-               for _ in range(3)) / 1e12
 
 
 def with_sustained(roof: dict, sustained):
@@ -120,9 +122,8 @@ def with_sustained(roof: dict, sustained):
     return roof
 
 
-def recorded_traffic(kernel: str, cfg: int, workload: str):
+def recorded_traffic(kernel: str, cfg: int, workload: str, src: str):
     """HBM bytes per launch (fetch + write) from a matching traffic-record, else None."""
-    src = kernel_source_hash()
     pat = re.compile(r"traffic-record:\s+kernel=(\S+)\s+cfg=(\S+)\s+workload=(\S+)\s+src=(\S+)"
                      r"\s+fetch_bytes=(\d+)\s+write_bytes=(\d+)")
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*"))):
@@ -204,60 +205,33 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + [BATCHED])
-    ap.add_argument("--plain-steps", type=int, default=2)
-    ap.add_argument("--fp64-steps", type=int, default=2,
-                    help="timed steps of the FP64-MFMA form (only for p < 2^26)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-probe", action="store_true",
-                    help="skip the sustained int8 MFMA rate probe (mh_probe_mfma_i8)")
-    ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--ablation", action="store_true",
-                    help="plain kernel through the planner against the elementwise comparator "
-                         "(per-element Morton-hybrid encoding, no planner) on --workload")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="built-in kernel configuration instead of tuning during warm-up")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        copy_calibration()
-        return
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: the library runs on a single MI355X and has "
-              "no multi-GPU path; run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-
-    if args.workload == BATCHED:
-        bench_batched(args)
-        return
-
+def single_workload(args, mh, name, steps, warmup, cpu_budget):
+    """One product of workload `name` (operands resident in HBM, Morton-hybrid
+    layout): the limb form timed over `steps` steps after `warmup` (the first
+    warm-up call tunes the configuration), then the plain comparator, the
+    FP64 form where p < 2^26, and the CPU oracle on a bounded sample.
+    Returns the fields of one bench line (the headline or an extra key)."""
     import torch
 
-    import paper_1705_04807_amd as mh
     from seeded_inputs import residues_torch
 
-    W = WORKLOADS[args.workload]
+    W = WORKLOADS[name]
     N, T, p, m, k, n = W["N"], W["T"], W["p"], W["m"], W["k"], W["n"]
     rc, cc, ra, ca, rb, cb = W["off"]
-    torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     sh = stream.cuda_stream
     ctx = mh.mh_ctx_create(0)
 
-    log("generating %s" % args.workload)
+    log("generating %s" % name)
     cart = {}
     parents = {}
-    for name, seed in zip("ABC", W["seeds"]):
+    for key, seed in zip("ABC", W["seeds"]):
         X = residues_torch(seed, p, N, N, device="cuda")
-        cart[name] = X
+        cart[key] = X
         Y = torch.empty(N * N, dtype=torch.int32, device="cuda")
         torch.cuda.synchronize()
         mh.check(mh.mh_layout_from_cartesian(ctx, Y.data_ptr(), X.data_ptr(), N, N, T, sh))
-        parents[name] = Y
+        parents[key] = Y
     torch.cuda.synchronize()
     stream.synchronize()
 
@@ -267,30 +241,27 @@ def main():
                                    rb, cb, m, k, n, p, T, mode, sh), "mh_matmul_modp")
 
     work = 2.0 * m * n * k
-    if args.ablation:
-        ablation(args, mh, ctx, step, stream, work, W)
-        return
     s, info = mh.mh_plan_describe(N, rc, cc, N, ra, ca, N, rb, cb, m, k, n, p, T,
                                   mh.MH_MODE_LIMB_I8)
     mh.check(s)
     L = info.limbs
 
-    # ---- limb MFMA form (the headline); the first warm-up call tunes the
-    # kernel configuration for this shape (untimed)
+    # ---- limb MFMA form; the first warm-up call tunes the kernel
+    # configuration for this shape (untimed)
     if not args.no_autotune:
         mh.check(mh.mh_ctx_set_autotune(ctx, 2))
-    log("warmup %d" % args.warmup)
-    for _ in range(max(args.warmup, 1)):
+    log("%s: warmup %d" % (name, warmup))
+    for _ in range(max(warmup, 1)):
         step(mh.MH_MODE_LIMB_I8)
     stream.synchronize()
     torch.cuda.synchronize()
     mh.mh_ctx_set_timing(ctx, True)
     for kk in range(mh.MH_K_COUNT):
         mh.mh_ctx_kernel_time(ctx, kk, reset=True)
-    log("timing %d steps" % args.steps)
+    log("%s: timing %d steps" % (name, steps))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step(mh.MH_MODE_LIMB_I8)
     stream.synchronize()
     torch.cuda.synchronize()
@@ -301,12 +272,12 @@ def main():
     kernel_cfg = tuned if tuned >= 0 else info.kernel_cfg
     pack_ms, pack_n = mh.mh_ctx_kernel_time(ctx, mh.MH_K_PACK, reset=True)
     mh.mh_ctx_set_timing(ctx, False)
-    ms_per_step = elapsed / args.steps * 1e3
-    value = work * args.steps / elapsed / 1e9
+    ms_per_step = elapsed / steps * 1e3
+    value = work * steps / elapsed / 1e9
     gemm_avg = gemm_ms / max(gemm_n, 1)
     int8_tops = L * L * work / (gemm_avg * 1e-3) / 1e12
-    log("limb: %.3f ms/step, gemm %.3f ms, pack %.3f ms" % (ms_per_step, gemm_avg,
-                                                           pack_ms / max(pack_n, 1)))
+    log("%s: limb %.3f ms/step, gemm %.3f ms, pack %.3f ms"
+        % (name, ms_per_step, gemm_avg, pack_ms / max(pack_n, 1)))
 
     # ---- plain uint32 kernel (comparator)
     plain = None
@@ -330,14 +301,7 @@ def main():
                               "unit": "T multiply-accumulates/s",
                               "frac": tmacs / PLAIN_PEAK_TMACS, "kernel": "k_gemm_plain"}}
         plain["limb_speedup"] = value / plain["value"]
-        if not args.no_probe:
-            log("sustained multiply-accumulate probe")
-            smacs = max(mh.mh_probe_valu_mac(ctx, VALU_PROBE_ITERS, sh) for _ in range(3)) / 1e12
-            plain["roofline"].update(
-                {"sustained_peak": smacs, "frac_sustained": tmacs / smacs,
-                 "sustained_note": "sustained_peak = issue rate of the same multiply-accumulate "
-                                   "pair with no memory traffic (mh_probe_valu_mac)"})
-        log("plain: %.3f ms/step" % plain["ms_per_step"])
+        log("%s: plain %.3f ms/step" % (name, plain["ms_per_step"]))
 
     # ---- FP64-MFMA form (primes below 2^26 only)
     fp64 = None
@@ -362,47 +326,163 @@ def main():
                              "unit": "TFLOP/s", "frac": ftf / FP64_PEAK_TFLOPS,
                              "kernel": "k_gemm_f64"}}
         fp64["limb_speedup"] = value / fp64["value"]
-        log("fp64: %.3f ms/step, gemm %.3f ms" % (fp64["ms_per_step"], fgemm))
+        log("%s: fp64 %.3f ms/step, gemm %.3f ms" % (name, fp64["ms_per_step"], fgemm))
     assert mh.mh_ctx_last_device_error(ctx) == 0
-    sustained = sustained_int8(mh, ctx, stream, args)
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline")
-        cpu = cpu_baseline(cart["A"], cart["B"], W)
+        log("%s: cpu baseline" % name)
+        cpu = cpu_baseline(cart["A"], cart["B"], W, budget_s=cpu_budget)
     mh.mh_ctx_destroy(ctx)
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "GOPS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
-        "config": {"workload": args.workload, "m": m, "k": k, "n": n, "p": p, "T": T,
+    del cart, parents
+    torch.cuda.empty_cache()
+    return {
+        "value": value, "unit": "GOPS", "steps": steps, "warmup": warmup,
+        "ms_per_step": ms_per_step,
+        "config": {"workload": name, "m": m, "k": k, "n": n, "p": p, "T": T,
                    "parents": N, "offsets_c_a_b": list(W["off"]), "limbs": L,
                    "mode": "limb_i8", "tile": [info.tile_m, info.tile_n]},
-        "roofline": with_sustained({
-                     "bound": "mfma", "achieved": int8_tops, "peak": INT8_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": int8_tops / INT8_PEAK_TOPS,
-                     "traffic": recorded_traffic("k_gemm_limb", kernel_cfg, args.workload),
+        "roofline": {"bound": "mfma", "achieved": int8_tops, "peak": INT8_PEAK_TOPS,
+                     "unit": INT8_UNIT, "frac": int8_tops / INT8_PEAK_TOPS,
+                     "traffic": recorded_traffic("k_gemm_limb", kernel_cfg, name,
+                                                 kernel_source_hash()),
                      "kernel": "k_gemm_limb", "kernel_cfg": kernel_cfg,
                      "kernel_src": kernel_source_hash(), "kernel_ms": gemm_avg,
                      "kernel_ms_min": min(gemm_each) if gemm_each else None,
                      "kernel_ms_median": (sorted(gemm_each)[len(gemm_each) // 2]
                                           if gemm_each else None),
-                     "note": "achieved = int8 ops (L^2 * 2mnk) per launch / average launch "
-                             "time; traffic = HBM bytes per launch from FETCH_SIZE and "
-                             "WRITE_SIZE, copy-calibrated"}, sustained),
+                     "note": "achieved = int8 multiply-add operations (L^2 * 2mnk) per launch "
+                             "/ average launch time, in tera-operations per second; traffic = "
+                             "HBM bytes per launch from FETCH_SIZE and WRITE_SIZE, "
+                             "copy-calibrated"},
         "pack_ms": pack_ms / max(pack_n, 1),
         "plain": plain,
         "fp64": fp64,
         "cpu_baseline": cpu,
     }
+
+
+def probes(args, mh):
+    """Measured ceilings, after every timed region: the sustained int8 MFMA
+    rate and the plain form's multiply-accumulate issue rate (None, None
+    with --no-probe)."""
+    if args.no_probe:
+        return None, None
+    import torch
+    stream = torch.cuda.Stream()
+    ctx = mh.mh_ctx_create(0)
+    log("sustained multiply-accumulate probe")
+    smacs = max(mh.mh_probe_valu_mac(ctx, VALU_PROBE_ITERS, stream.cuda_stream)
+                for _ in range(3)) / 1e12
+    log("sustained int8 MFMA probe")
+    sint8 = max(mh.mh_probe_mfma_i8(ctx, PROBE_ITERS, stream.cuda_stream)
+                for _ in range(3)) / 1e12
+    mh.mh_ctx_destroy(ctx)
+    return sint8, smacs
+
+
+def with_plain_sustained(plain, smacs):
+    if plain and smacs and "roofline" in plain:
+        r = plain["roofline"]
+        r.update({"sustained_peak": smacs, "frac_sustained": r["achieved"] / smacs,
+                  "sustained_note": "sustained_peak = issue rate of the same multiply-accumulate "
+                                    "pair with no memory traffic (mh_probe_valu_mac)"})
+    return plain
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + [BATCHED])
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=2,
+                    help="timed steps of the FP64-MFMA form (only for p < 2^26)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the sustained-rate probes (mh_probe_mfma_i8, mh_probe_valu_mac)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="the default run measures only the 8192^3 product, without the "
+                         "4096^3, non-aligned and 512-product batch workloads beside it")
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--ablation", action="store_true",
+                    help="plain kernel through the planner against the elementwise comparator "
+                         "(per-element Morton-hybrid encoding, no planner) on --workload")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="built-in kernel configuration instead of tuning during warm-up")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the library runs on a single MI355X and has "
+              "no multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1705_04807_amd as mh
+    torch.cuda.set_device(0)
+
+    if args.ablation:
+        ablation(args, mh)
+        return
+
+    extras = {}
+    if args.workload == BATCHED:
+        head = batched_workload(args, mh, args.steps, args.warmup, 12.0)
+    else:
+        head = single_workload(args, mh, args.workload, args.steps, args.warmup, 12.0)
+        if args.workload == DEFAULT and not args.no_extras:
+            # the other workloads of the metric, each with its own roofline and
+            # CPU baseline (smaller samples), after the headline's timed region
+            for key, name in EXTRA_SINGLE:
+                extras[key] = single_workload(args, mh, name, args.steps, args.warmup, 4.0)
+            extras[EXTRA_BATCHED] = batched_workload(args, mh, args.steps, args.warmup, 4.0)
+    sint8, smacs = probes(args, mh)
+    for part in [head] + list(extras.values()):
+        with_sustained(part["roofline"], sint8)
+        with_plain_sustained(part.get("plain"), smacs)
+
+    out = {"metric": METRIC, "value": head["value"], "unit": "GOPS", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i8",
+           "data": "synthetic", "config": head["config"], "roofline": head["roofline"]}
+    for key, val in head.items():
+        if key not in out and key not in ("steps", "warmup", "unit"):
+            out[key] = val
+    out.update(extras)
     print(json.dumps(out), flush=True)
 
 
-def ablation(args, mh, ctx, step, stream, work, W):
+def ablation(args, mh):
     """Problems P1/P2 of section 2.1 on the GPU: one kernel, two ways of reaching the
     operands.  Prints one JSON line (not the throughput line)."""
     import torch
+
+    from seeded_inputs import residues_torch
+
+    W = WORKLOADS[args.workload]
+    N, T, p, m, k, n = W["N"], W["T"], W["p"], W["m"], W["k"], W["n"]
+    rc, cc, ra, ca, rb, cb = W["off"]
+    stream = torch.cuda.Stream()
+    sh = stream.cuda_stream
+    ctx = mh.mh_ctx_create(0)
+    parents = {}
+    for key, seed in zip("ABC", W["seeds"]):
+        X = residues_torch(seed, p, N, N, device="cuda")
+        Y = torch.empty(N * N, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        mh.check(mh.mh_layout_from_cartesian(ctx, Y.data_ptr(), X.data_ptr(), N, N, T, sh))
+        parents[key] = Y
+    stream.synchronize()
+    work = 2.0 * m * n * k
+
+    def step(mode):
+        mh.check(mh.mh_matmul_modp(ctx, parents["C"].data_ptr(), N, rc, cc,
+                                   parents["A"].data_ptr(), N, ra, ca, parents["B"].data_ptr(), N,
+                                   rb, cb, m, k, n, p, T, mode, sh), "mh_matmul_modp")
 
     def timed(mode, kernel):
         step(mode)
@@ -437,22 +517,22 @@ def ablation(args, mh, ctx, step, stream, work, W):
           flush=True)
 
 
-def bench_batched(args):
-    """One step = one mh_matmul_modp_batched call over the 512 products."""
-    import numpy as np
+def batched_workload(args, mh, steps, warmup, cpu_budget):
+    """One step = one mh_matmul_modp_batched call over the 512 products of one
+    TU recursion level; beside it a loop of single mh_matmul_modp calls and
+    the plain form's batch (products one after another).  Returns the fields
+    of one bench line."""
     import torch
 
-    import paper_1705_04807_amd as mh
     from seeded_inputs import residues_torch, tu_level_batch
 
     N, T, p, nC = 8192, 64, 65521, 64
     calls = tu_level_batch(seed=5000, count=512, N=N, n_c_parents=nC)
     work = float(sum(2 * c["m"] * c["k"] * c["n"] for c in calls))
-    torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     sh = stream.cuda_stream
     ctx = mh.mh_ctx_create(0)
-    log("generating %d parents" % (nC + 2))
+    log("batched: generating %d parents" % (nC + 2))
 
     def parent(seed):
         X = residues_torch(seed, p, N, N, device="cuda")
@@ -479,69 +559,76 @@ def bench_batched(args):
                                        A.data_ptr(), N, c["ra"], c["ca"], B.data_ptr(), N,
                                        c["rb"], c["cb"], c["m"], c["k"], c["n"], p, T, mode, sh))
 
-    def timed(fn, steps, kernels=()):
+    def timed(fn, nsteps, kernels=()):
         stream.synchronize()
         mh.mh_ctx_set_timing(ctx, True)
         for kk in range(mh.MH_K_COUNT):
             mh.mh_ctx_kernel_time(ctx, kk, reset=True)
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for _ in range(nsteps):
             fn()
         stream.synchronize()
         el = time.perf_counter() - t0
         ks = {kk: mh.mh_ctx_kernel_time(ctx, kk, reset=True) for kk in kernels}
         mh.mh_ctx_set_timing(ctx, False)
-        return el / steps, ks
+        return el / nsteps, ks
 
     if not args.no_autotune:
         mh.check(mh.mh_ctx_set_autotune(ctx, 2))
-    log("warmup %d" % args.warmup)
-    for _ in range(max(args.warmup, 1)):
+    log("batched: warmup %d" % warmup)
+    for _ in range(max(warmup, 1)):
         batched(mh.MH_MODE_LIMB_I8)
-    t_b, ks = timed(lambda: batched(mh.MH_MODE_LIMB_I8), args.steps, (mh.MH_K_BATCHED,))
+    t_b, ks = timed(lambda: batched(mh.MH_MODE_LIMB_I8), steps, (mh.MH_K_BATCHED,))
     graph_ms = ks[mh.MH_K_BATCHED][0] / max(ks[mh.MH_K_BATCHED][1], 1)
+    s, batch_cfg, L = mh.mh_ctx_last_batch_config(ctx)
+    mh.check(s)
     value = work / t_b / 1e9
-    log("batched: %.3f ms/step (graph %.3f ms)" % (t_b * 1e3, graph_ms))
+    log("batched: %.3f ms/step (graph %.3f ms, configuration %d)" % (t_b * 1e3, graph_ms,
+                                                                      batch_cfg))
     looped(mh.MH_MODE_LIMB_I8)
-    t_l, _ = timed(lambda: looped(mh.MH_MODE_LIMB_I8), 1)
-    log("looped: %.3f ms" % (t_l * 1e3))
+    t_l, _ = timed(lambda: looped(mh.MH_MODE_LIMB_I8), 2)
+    log("batched: looped %.3f ms" % (t_l * 1e3))
     plain = None
     if args.plain_steps > 0:
-        t_p, _ = timed(lambda: batched(mh.MH_MODE_PLAIN_U32), 1)
+        batched(mh.MH_MODE_PLAIN_U32)
+        t_p, _ = timed(lambda: batched(mh.MH_MODE_PLAIN_U32), max(args.plain_steps, 3))
         plain = {"value": work / t_p / 1e9, "unit": "GOPS", "ms_per_step": t_p * 1e3,
-                 "limb_speedup": value / (work / t_p / 1e9)}
-        log("plain: %.3f ms" % (t_p * 1e3))
+                 "steps": max(args.plain_steps, 3), "limb_speedup": value / (work / t_p / 1e9)}
+        log("batched: plain %.3f ms" % (t_p * 1e3))
     assert mh.mh_ctx_last_device_error(ctx) == 0
-    sustained = sustained_int8(mh, ctx, stream, args)
-    L = 2
     int8_tops = L * L * work / (graph_ms * 1e-3) / 1e12
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline")
+        log("batched: cpu baseline")
         c0 = max(calls, key=lambda c: c["m"] * c["n"] * c["k"])
         W = dict(p=p, m=c0["m"], k=c0["k"], n=c0["n"],
                  off=(c0["rc"], c0["cc"], c0["ra"], c0["ca"], c0["rb"], c0["cb"]))
-        cpu = cpu_baseline(Acart.view(N, N), Bcart.view(N, N), W)
+        cpu = cpu_baseline(Acart.view(N, N), Bcart.view(N, N), W, budget_s=cpu_budget)
         cpu["sample"] = "largest product of the batch: " + cpu["sample"]
     mh.mh_ctx_destroy(ctx)
-    out = {
-        "metric": METRIC, "value": value, "unit": "GOPS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": t_b * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+    del Acart, Bcart, A, B, Cs
+    torch.cuda.empty_cache()
+    src = kernel_source_hash(BATCHED_SOURCES)
+    return {
+        "value": value, "unit": "GOPS", "steps": steps, "warmup": warmup,
+        "ms_per_step": t_b * 1e3,
         "config": {"workload": BATCHED, "products": len(calls), "work_2mnk": work, "p": p,
                    "T": T, "parents": N, "c_parents": nC, "limbs": L, "mode": "limb_i8",
                    "form": "persistent pack + GEMM in one HIP graph"},
-        "roofline": with_sustained({
-                     "bound": "mfma", "achieved": int8_tops, "peak": INT8_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": int8_tops / INT8_PEAK_TOPS, "traffic": None,
+        "roofline": {"bound": "mfma", "achieved": int8_tops, "peak": INT8_PEAK_TOPS,
+                     "unit": INT8_UNIT, "frac": int8_tops / INT8_PEAK_TOPS,
+                     "traffic": recorded_traffic("batched_graph", batch_cfg, BATCHED, src),
                      "kernel": "batched graph (k_pack_limb_batched + k_gemm_limb_batched)",
-                     "kernel_ms": graph_ms,
-                     "note": "achieved = int8 ops of the whole batch / graph time"}, sustained),
-        "looped": {"value": work / t_l / 1e9, "unit": "GOPS", "ms_per_step": t_l * 1e3},
+                     "kernel_cfg": batch_cfg, "kernel_src": src, "kernel_ms": graph_ms,
+                     "note": "achieved = int8 multiply-add operations of the whole batch "
+                             "(L^2 * sum 2mnk) / graph time, in tera-operations per second; "
+                             "traffic = HBM bytes per graph launch (both pack kernels and the "
+                             "GEMM) from FETCH_SIZE and WRITE_SIZE, copy-calibrated"},
+        "looped": {"value": work / t_l / 1e9, "unit": "GOPS", "ms_per_step": t_l * 1e3,
+                   "steps": 2},
         "plain": plain,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -347,6 +347,12 @@ typedef struct {
 mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *descs, int32_t count,
                                  uint32_t p, int32_t T, int32_t mode, hipStream_t stream);
 
+/* Kernel configuration (index into the limb kernel table, as reported by
+ * mh_plan_info.kernel_cfg) and limb count of the last batched graph the
+ * context launched for a caller (tuning runs excluded); -1 and 0 if none.
+ * Either pointer may be null. */
+mh_status mh_ctx_last_batch_config(mh_ctx *ctx, int32_t *cfg, int32_t *limbs);
+
 /* ------------------------------------------------------ planner, host only */
 
 /* What the planner makes of one product (no device work, no validation of

@@ -21,6 +21,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mh_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# MH_SANITIZE=1: the AddressSanitizer / UndefinedBehaviorSanitizer build of
+# build_sanitized.py, for host-only sanitizer runs of the CPU tests.
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
 
 ALIGNED, CONTAINED, QUADRANT = 1, 2, 4
 
@@ -41,9 +44,15 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        L = ct.CDLL(_LIB)
+        if os.environ.get("MH_SANITIZE") == "1":
+            if not os.path.exists(_LIB_SAN):
+                raise ImportError("MH_SANITIZE=1 but oracle/liboracle_san.so is not built "
+                                  "(python oracle/build_sanitized.py)")
+            L = ct.CDLL(_LIB_SAN)
+        else:
+            if not os.path.exists(_LIB):
+                build()
+            L = ct.CDLL(_LIB)
         P = ct.c_void_p
         I64 = ct.c_int64
         U32 = ct.c_uint32

@@ -18,7 +18,10 @@ import ctypes as ct
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmh.so")
+# MH_SANITIZE=1 selects the build whose host code runs under AddressSanitizer
+# and UndefinedBehaviorSanitizer (build_sanitized.py; CPU-only test runs).
+LIB_PATH = os.path.join(_HERE, "libmh_san.so" if os.environ.get("MH_SANITIZE") == "1"
+                        else "libmh.so")
 
 MH_OK = 0
 MH_E_INVALID = 1
@@ -60,7 +63,7 @@ EXPORTS = (
     "mh_ctx_tune_cache_load", "mh_parent_size", "mh_layout_from_cartesian_padded",
     "mh_layout_to_cartesian_padded", "mh_ctx_kernel_times", "mh_probe_mfma_i8",
     "mh_probe_valu_mac", "mh_ctx_set_workspace_limit", "mh_ctx_workspace_info",
-    "mh_matmul_modp_noalloc",
+    "mh_matmul_modp_noalloc", "mh_ctx_last_batch_config",
 )
 
 
@@ -131,6 +134,7 @@ def _load():
         "mh_matmul_modp_noalloc": ([P, P, I64, I64, I64, P, I64, I64, I64, P, I64, I64, I64, I64,
                                     I64, I64, U32, I32, I32, P], ct.c_int),
         "mh_matmul_modp_batched": ([P, ct.POINTER(mh_mm_desc), I32, U32, I32, I32, P], ct.c_int),
+        "mh_ctx_last_batch_config": ([P, ct.POINTER(I32), ct.POINTER(I32)], ct.c_int),
         "mh_plan_describe": ([I64] * 12 + [U32, I32, I32, ct.POINTER(mh_plan_info)], ct.c_int),
         "mh_plan_leaves": ([I64] * 12 + [I32, ct.POINTER(I64), I64, ct.POINTER(I64)], ct.c_int),
         "mh_plan_gemm_tasks": ([I64] * 12 + [U32, I32, I32, ct.POINTER(I64), I64,
@@ -316,6 +320,13 @@ def mh_matmul_modp_batched(ctx, descs, count: int, p: int, T: int,
 
 
 # ----------------------------------------------------------------- planner
+
+def mh_ctx_last_batch_config(ctx) -> tuple[int, int, int]:
+    """(status, cfg, limbs) of the last batched graph the context launched."""
+    cfg, limbs = ct.c_int32(-1), ct.c_int32(0)
+    s = lib.mh_ctx_last_batch_config(ctx, ct.byref(cfg), ct.byref(limbs))
+    return s, cfg.value, limbs.value
+
 
 def mh_plan_describe(NC, rc, cc, NA, ra, ca, NB, rb, cb, m, k, n, p, T, mode=MH_MODE_AUTO):
     """Returns (status, mh_plan_info)."""

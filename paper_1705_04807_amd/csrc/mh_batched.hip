@@ -299,12 +299,24 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
     record_start(ctx, MH_K_BATCHED, stream, t);
     e = hipGraphLaunch(exec, stream);
     record_end(ctx, stream, t);
+    if (e == hipSuccess && !c_override) {
+        b.last_cfg = cfg;
+        b.last_L = L;
+    }
     return note_error(ctx, e);
 }
 
 }  // namespace mh
 
 using namespace mh;
+
+extern "C" mh_status mh_ctx_last_batch_config(mh_ctx *ctx, int32_t *cfg, int32_t *limbs)
+{
+    if (!ctx) return MH_E_INVALID;
+    if (cfg) *cfg = ctx->batched.last_cfg;
+    if (limbs) *limbs = ctx->batched.last_L;
+    return MH_OK;
+}
 
 extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, int32_t count,
                                             uint32_t p, int32_t T, int32_t mode,

@@ -35,6 +35,8 @@ struct BatchedState {
         hipGraphExec_t exec = nullptr;
     };
     std::map<int, Captured> graphs;
+    int last_cfg = -1;                  // configuration and limbs of the last batched graph
+    int last_L = 0;
 };
 
 struct DeviceGuard {

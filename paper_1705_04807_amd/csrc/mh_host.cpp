@@ -19,7 +19,11 @@ using namespace mh;
 
 extern "C" const char *mh_status_string(mh_status s)
 {
-    switch (s) {
+    // A C caller may pass any int: read the argument's bits as one, since
+    // loading an enum value outside the enumerators' range is undefined in C++.
+    int v;
+    std::memcpy(&v, &s, sizeof v);
+    switch (v) {
     case MH_OK: return "ok";
     case MH_E_INVALID: return "invalid argument";
     case MH_E_SHAPE: return "parent size is not T * 2^q";

@@ -3,8 +3,8 @@
 // One workgroup converts whole tiles.  The Morton-hybrid side of a tile is
 // T*T contiguous words (section 1; Prop. 2.5 row-major tiles), so it is read
 // or written as one contiguous run; the Cartesian side is T row segments of
-// T words.  The tile coordinates come from de-interleaving the tile's Z
-// index once per tile, never per element.  HBM-bound: 4 bytes read and
+// T words.  The tile coordinates come from de-interleaving each tile's Z
+// index once, into a table in LDS, never per element.  HBM-bound: 4 bytes read and
 // 4 bytes written per word.
 #include "mh_internal.h"
 
@@ -19,6 +19,7 @@ __host__ __device__ constexpr int tiles_per_group(int logT)
 {
     return (2 * logT >= 12) ? 1 : (1 << (12 - 2 * logT));
 }
+constexpr int kMaxTilesPerGroup = tiles_per_group(4);  // T = 16, the smallest edge
 
 // Cartesian side: rows x cols words (row length ld); the Morton-hybrid
 // parent is padded beyond them: TO_MH writes zeros there, the other way
@@ -36,13 +37,22 @@ __global__ __launch_bounds__(kThreads) void k_layout(uint32_t *__restrict__ dst,
     const int words = T << logT;                 // per tile
     const int per_group = tpg * words;
     constexpr int W = VEC ? 4 : 1;
+    // The group's tiles, de-interleaved once each: tile coordinates are
+    // below 2^14 (N <= 2^18, T >= 16), so Z indices fit 32 bits.
+    __shared__ uint32_t tileI[kMaxTilesPerGroup], tileJ[kMaxTilesPerGroup];
+    if (int(threadIdx.x) < tpg) {
+        const uint32_t tz = uint32_t(tile0 + threadIdx.x);
+        tileI[threadIdx.x] = compact16(tz >> 1);
+        tileJ[threadIdx.x] = compact16(tz);
+    }
+    __syncthreads();
     for (int e = threadIdx.x * W; e < per_group; e += kThreads * W) {
-        const uint64_t tz = tile0 + (e >> (2 * logT));
+        const int tl = e >> (2 * logT);
+        const uint64_t tz = tile0 + tl;
         if (tz >= ntiles) break;
         const int r = (e >> logT) & (T - 1);
         const int c = e & (T - 1);
-        const uint64_t I = compact32(tz >> 1), J = compact32(tz);
-        const int64_t gi = int64_t(I << logT) + r, gj = int64_t(J << logT) + c;
+        const int64_t gi = (int64_t(tileI[tl]) << logT) + r, gj = (int64_t(tileJ[tl]) << logT) + c;
         const bool inside = gi < rows && gj < cols;  // whole group when VEC
         const uint64_t cart = uint64_t(gi) * uint64_t(ld) + uint64_t(gj);
         const uint64_t mh = (tz << (2 * logT)) + (uint64_t(r) << logT) + c;
