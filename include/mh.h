@@ -347,6 +347,19 @@ typedef struct {
 mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *descs, int32_t count,
                                  uint32_t p, int32_t T, int32_t mode, hipStream_t stream);
 
+/* The checks of mh_matmul_modp_batched without the product, host only: each
+ * product's sizes, bounds, modulus and form as for mh_matmul_modp (pointers
+ * must be non-null and aligned but are never dereferenced), and no output
+ * block sharing a word with another output block or any input block of the
+ * batch (section 2.2, Prop. 2.6: the independent calls of one recursion
+ * level write disjoint blocks).  Returns what mh_matmul_modp_batched would
+ * return before any device work: MH_OK, MH_E_INVALID, MH_E_SHAPE,
+ * MH_E_BOUNDS, MH_E_MODULUS, MH_E_ALIAS or MH_E_UNSUPPORTED.  The aliasing
+ * check sorts the blocks of each parent by first row and sweeps them, so a
+ * batch of n products costs O(n log n) plus the pairs whose rows overlap. */
+mh_status mh_validate_batch(const mh_mm_desc *descs, int32_t count, uint32_t p, int32_t T,
+                            int32_t mode);
+
 /* Kernel configuration (index into the limb kernel table, as reported by
  * mh_plan_info.kernel_cfg) and limb count of the last batched graph the
  * context launched for a caller (tuning runs excluded); -1 and 0 if none.

@@ -63,7 +63,7 @@ EXPORTS = (
     "mh_ctx_tune_cache_load", "mh_parent_size", "mh_layout_from_cartesian_padded",
     "mh_layout_to_cartesian_padded", "mh_ctx_kernel_times", "mh_probe_mfma_i8",
     "mh_probe_valu_mac", "mh_ctx_set_workspace_limit", "mh_ctx_workspace_info",
-    "mh_matmul_modp_noalloc", "mh_ctx_last_batch_config",
+    "mh_matmul_modp_noalloc", "mh_ctx_last_batch_config", "mh_validate_batch",
 )
 
 
@@ -135,6 +135,7 @@ def _load():
                                     I64, I64, U32, I32, I32, P], ct.c_int),
         "mh_matmul_modp_batched": ([P, ct.POINTER(mh_mm_desc), I32, U32, I32, I32, P], ct.c_int),
         "mh_ctx_last_batch_config": ([P, ct.POINTER(I32), ct.POINTER(I32)], ct.c_int),
+        "mh_validate_batch": ([ct.POINTER(mh_mm_desc), I32, U32, I32, I32], ct.c_int),
         "mh_plan_describe": ([I64] * 12 + [U32, I32, I32, ct.POINTER(mh_plan_info)], ct.c_int),
         "mh_plan_leaves": ([I64] * 12 + [I32, ct.POINTER(I64), I64, ct.POINTER(I64)], ct.c_int),
         "mh_plan_gemm_tasks": ([I64] * 12 + [U32, I32, I32, ct.POINTER(I64), I64,
@@ -320,6 +321,10 @@ def mh_matmul_modp_batched(ctx, descs, count: int, p: int, T: int,
 
 
 # ----------------------------------------------------------------- planner
+
+def mh_validate_batch(descs, count: int, p: int, T: int, mode: int = MH_MODE_AUTO) -> int:
+    return lib.mh_validate_batch(descs, count, p, T, mode)
+
 
 def mh_ctx_last_batch_config(ctx) -> tuple[int, int, int]:
     """(status, cfg, limbs) of the last batched graph the context launched."""

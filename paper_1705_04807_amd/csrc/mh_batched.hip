@@ -138,23 +138,74 @@ hipGraphExec_t ensure_graph(mh_ctx *ctx, int cfg, int L)
     return ex;
 }
 
-bool block_overlap(const uint32_t *X, int64_t NX, int64_t rx, int64_t cx, int64_t xr, int64_t xc,
-                   const uint32_t *Y, int64_t NY, int64_t ry, int64_t cy, int64_t yr, int64_t yc)
+// One rectangle of a batch in the storage of a parent: an output block
+// (is_c) or an input block.
+struct Rect {
+    int64_t r0, r1, c0, c1;  // rows [r0, r1), columns [c0, c1)
+    bool is_c;
+};
+
+// MH_E_ALIAS if an output block of the batch shares a word with another
+// output block or with any input block, else MH_OK; the rule of
+// output_aliases applied to every pair, in O(n log n + overlaps) instead of
+// O(n^2) (a TU level has hundreds of products).  Blocks of different parent
+// allocations never share words; if two different parents' storage
+// overlaps (another base or edge), any block of one against an output block
+// of the other counts as overlapping, as it does for a single product.
+mh_status check_batch_aliasing(const std::vector<Product> &prods)
 {
-    Product a{}, b{};
-    a.C = const_cast<uint32_t *>(X);
-    a.NC = NX;
-    a.rc = rx;
-    a.cc = cx;
-    a.m = xr;
-    a.n = xc;
-    b.C = const_cast<uint32_t *>(Y);
-    b.NC = NY;
-    b.rc = ry;
-    b.cc = cy;
-    b.m = yr;
-    b.n = yc;
-    return outputs_alias(a, b);
+    struct Parent {
+        const uint32_t *base;
+        int64_t N;
+        std::vector<Rect> rects;
+        bool has_c = false;
+    };
+    std::vector<Parent> parents;
+    auto parent_of = [&](const uint32_t *base, int64_t N) -> Parent & {
+        for (Parent &q : parents)
+            if (q.base == base && q.N == N) return q;
+        parents.push_back(Parent{base, N, {}, false});
+        return parents.back();
+    };
+    auto add = [&](const uint32_t *base, int64_t N, int64_t r, int64_t c, int64_t rows,
+                   int64_t cols, bool is_c) {
+        if (rows <= 0 || cols <= 0) return;
+        Parent &q = parent_of(base, N);
+        q.rects.push_back(Rect{r, r + rows, c, c + cols, is_c});
+        q.has_c = q.has_c || is_c;
+    };
+    for (const Product &x : prods) {
+        if (x.m > 0 && x.n > 0) add(x.C, x.NC, x.rc, x.cc, x.m, x.n, true);
+        add(x.A, x.NA, x.ra, x.ca, x.m, x.k, false);
+        add(x.B, x.NB, x.rb, x.cb, x.k, x.n, false);
+    }
+    // Distinct parents whose storage overlaps: sweep over start addresses.
+    std::vector<size_t> by_addr(parents.size());
+    std::iota(by_addr.begin(), by_addr.end(), 0);
+    auto lo = [&](size_t q) { return (uintptr_t)parents[q].base; };
+    auto hi = [&](size_t q) { return lo(q) + 4 * (uintptr_t)(parents[q].N * parents[q].N); };
+    std::sort(by_addr.begin(), by_addr.end(), [&](size_t a, size_t b) { return lo(a) < lo(b); });
+    for (size_t u = 0; u < by_addr.size(); ++u)
+        for (size_t v = u + 1; v < by_addr.size() && lo(by_addr[v]) < hi(by_addr[u]); ++v)
+            if (parents[by_addr[u]].has_c || parents[by_addr[v]].has_c) return MH_E_ALIAS;
+    // Within one parent: sweep the rectangles by first row, keeping those
+    // whose rows are still open; a pair counts when one is an output block.
+    for (Parent &q : parents) {
+        if (!q.has_c) continue;
+        std::vector<Rect> &rs = q.rects;
+        std::sort(rs.begin(), rs.end(), [](const Rect &a, const Rect &b) { return a.r0 < b.r0; });
+        std::vector<const Rect *> open;
+        for (const Rect &x : rs) {
+            size_t keep = 0;
+            for (const Rect *y : open)
+                if (y->r1 > x.r0) open[keep++] = y;
+            open.resize(keep);
+            for (const Rect *y : open)
+                if ((x.is_c || y->is_c) && x.c0 < y->c1 && y->c0 < x.c1) return MH_E_ALIAS;
+            open.push_back(&x);
+        }
+    }
+    return MH_OK;
 }
 
 }  // namespace
@@ -318,23 +369,20 @@ extern "C" mh_status mh_ctx_last_batch_config(mh_ctx *ctx, int32_t *cfg, int32_t
     return MH_OK;
 }
 
-extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, int32_t count,
-                                            uint32_t p, int32_t T, int32_t mode,
-                                            hipStream_t stream)
+// Validation of a batched call, host only: every product as for a single
+// call, then the aliasing rule over the whole batch.
+static mh_status validate_batch(const mh_mm_desc *d, int32_t count, uint32_t p, int32_t T,
+                                int32_t mode, std::vector<Product> &prods, int &form, bool &sub)
 {
-    if (!ctx || count < 0 || (count > 0 && !d)) return MH_E_INVALID;
-    int form;
-    bool sub;
+    if (count < 0 || (count > 0 && !d)) return MH_E_INVALID;
     if (!parse_mode(mode, form, sub)) return MH_E_UNSUPPORTED;
-    mode = form;
     if (!valid_T(T)) return MH_E_UNSUPPORTED;
     if (p < 2u || p > 0x7FFFFFFFu) return MH_E_MODULUS;
     if (check_form_modulus(form, p) != MH_OK) return MH_E_MODULUS;
     // Validate every product first: a failing call has no effect.
-    std::vector<Product> prods(count);
+    prods.assign(size_t(count), Product{});
     for (int32_t i = 0; i < count; ++i) {
         Product &pr = prods[i];
-        pr = Product{};
         pr.C = d[i].C;
         pr.A = d[i].A;
         pr.B = d[i].B;
@@ -357,19 +405,29 @@ extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, in
         if (s != MH_OK) return s;
     }
     // No output block may overlap another output block or any input block.
-    for (int32_t i = 0; i < count; ++i) {
-        const Product &x = prods[i];
-        if (x.m == 0 || x.n == 0) continue;
-        for (int32_t j = 0; j < count; ++j) {
-            const Product &y = prods[j];
-            if (j != i && y.m > 0 && y.n > 0 &&
-                block_overlap(x.C, x.NC, x.rc, x.cc, x.m, x.n, y.C, y.NC, y.rc, y.cc, y.m, y.n))
-                return MH_E_ALIAS;
-            if (block_overlap(x.C, x.NC, x.rc, x.cc, x.m, x.n, y.A, y.NA, y.ra, y.ca, y.m, y.k) ||
-                block_overlap(x.C, x.NC, x.rc, x.cc, x.m, x.n, y.B, y.NB, y.rb, y.cb, y.k, y.n))
-                return MH_E_ALIAS;
-        }
-    }
+    return check_batch_aliasing(prods);
+}
+
+extern "C" mh_status mh_validate_batch(const mh_mm_desc *d, int32_t count, uint32_t p, int32_t T,
+                                       int32_t mode)
+{
+    std::vector<Product> prods;
+    int form;
+    bool sub;
+    return validate_batch(d, count, p, T, mode, prods, form, sub);
+}
+
+extern "C" mh_status mh_matmul_modp_batched(mh_ctx *ctx, const mh_mm_desc *d, int32_t count,
+                                            uint32_t p, int32_t T, int32_t mode,
+                                            hipStream_t stream)
+{
+    if (!ctx) return MH_E_INVALID;
+    std::vector<Product> prods;
+    int form;
+    bool sub;
+    if (mh_status st = validate_batch(d, count, p, T, mode, prods, form, sub); st != MH_OK)
+        return st;
+    mode = form;
     DeviceGuard g(ctx->device);
     std::vector<int32_t> live;
     for (int32_t i = 0; i < count; ++i)

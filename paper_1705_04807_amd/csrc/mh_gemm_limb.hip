@@ -119,18 +119,50 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
                 if (gam < a.sc || gam >= a.sc + a.n) return;
                 const uint32_t colC = uint32_t(a.col0C + gam);
                 const uint32_t colbits = spread16(colC >> a.logT), colin = colC & tmask;
-                static_for<16>([&](auto v) {
-                    const int row = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-                    const int64_t rho = rho0 + row;
-                    if (rho < a.sr || rho >= a.sr + a.m) return;
-                    const uint32_t rowC = rowC0 + uint32_t(row);
+                auto row_of = [&](int v) { return (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3); };
+                auto inside = [&](int v) {
+                    const int64_t rho = rho0 + row_of(v);
+                    return rho >= a.sr && rho < a.sr + a.m;
+                };
+                auto offset = [&](int v) {
+                    const uint32_t rowC = rowC0 + uint32_t(row_of(v));
                     const uint32_t tile = rowbits[v >= 8 ? 1 : 0] | colbits;
-                    const uint64_t off = (uint64_t(tile) << (2 * a.logT)) |
-                                         ((rowC & tmask) << a.logT) | colin;
-                    uint32_t c = a.C[off] + uint32_t(r[i][j][v]);
-                    if (c >= a.p) c -= a.p;
-                    a.C[off] = c;
-                });
+                    return (uint64_t(tile) << (2 * a.logT)) | ((rowC & tmask) << a.logT) | colin;
+                };
+                if constexpr (WM * WN == 1) {
+                    // The C loads of eight outputs first, then their
+                    // stores: in the other order each load would wait for
+                    // the store before it (the compiler cannot tell the
+                    // words apart), one memory round trip per output.
+                    static_for<2>([&](auto h) {
+                        uint32_t cv[8];
+                        static_for<8>([&](auto u) {
+                            constexpr int v = int(h) * 8 + int(u);
+                            cv[u] = inside(v) ? a.C[offset(v)] : 0u;
+                        });
+                        static_for<8>([&](auto u) {
+                            constexpr int v = int(h) * 8 + int(u);
+                            if (!inside(v)) return;
+                            uint32_t c = cv[u] + uint32_t(r[i][j][v]);
+                            if (c >= a.p) c -= a.p;
+                            a.C[offset(v)] = c;
+                        });
+                    });
+                } else {
+                    // (larger wave tiles have no registers to spare for that)
+                    static_for<16>([&](auto v) {
+                        const int row = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+                        const int64_t rho = rho0 + row;
+                        if (rho < a.sr || rho >= a.sr + a.m) return;
+                        const uint32_t rowC = rowC0 + uint32_t(row);
+                        const uint32_t tile = rowbits[v >= 8 ? 1 : 0] | colbits;
+                        const uint64_t off = (uint64_t(tile) << (2 * a.logT)) |
+                                             ((rowC & tmask) << a.logT) | colin;
+                        uint32_t c = a.C[off] + uint32_t(r[i][j][v]);
+                        if (c >= a.p) c -= a.p;
+                        a.C[off] = c;
+                    });
+                }
             });
         });
     };

@@ -282,3 +282,84 @@ def test_gemm_tasks_partition_output_in_whole_tiles(mode, seed):
             whole = (o % T == 0 or o == lo) and (e % T == 0 or e == hi)
             assert inside_one or whole
     assert (cover == 1).all()
+
+
+def _brute_alias(items):
+    """The aliasing rule of a batch, pair by pair: an output block may share a
+    word with no other output block and no input block; blocks of parents
+    whose storage overlaps with another base or edge count as overlapping."""
+    def blocks(it):
+        return ((it["C"], it["NC"], it["rc"], it["cc"], it["m"], it["n"]),
+                (it["A"], it["NA"], it["ra"], it["ca"], it["m"], it["k"]),
+                (it["B"], it["NB"], it["rb"], it["cb"], it["k"], it["n"]))
+
+    def alias(x, y):
+        (px, nx, rx, cx, hx, wx), (py, ny, ry, cy, hy, wy) = x, y
+        if min(hx, wx, hy, wy) <= 0:
+            return False
+        if px + 4 * nx * nx <= py or py + 4 * ny * ny <= px:
+            return False
+        if px != py or nx != ny:
+            return True
+        return rx < ry + hy and ry < rx + hx and cx < cy + wy and cy < cx + wx
+
+    for i, x in enumerate(items):
+        cx = blocks(x)[0]
+        for j, y in enumerate(items):
+            cy, ay, by = blocks(y)
+            if (j != i and alias(cx, cy)) or alias(cx, ay) or alias(cx, by):
+                return True
+    return False
+
+
+def test_validate_batch_against_pairwise_rule():
+    """mh_validate_batch (the checks of a batched call, host only; its
+    aliasing test is a sweep per parent) against the rule applied to every
+    pair, on random batches over a few parents, some of them placed so that
+    their storage overlaps another parent's."""
+    g = np.random.default_rng(17)
+    T, p = 64, 65521
+    for trial in range(300):
+        # parents: (base, N); bases are never dereferenced
+        base = 1 << 32
+        parents = [(base, 1024), (base + 4 * 1024 * 1024, 512), (base + (8 << 20), 1024)]
+        if trial % 5 == 0:  # another parent inside the first one's storage
+            parents.append((base + 4096 * 16, 256))
+        items = []
+        # odd trials: outputs in a parent of their own and smaller blocks, so
+        # that disjoint batches are as common as overlapping ones
+        sep, div = trial % 2 == 1, 2 if trial % 2 == 0 else 8
+        for _ in range(int(g.integers(1, 12))):
+            def pick(lo=0, hi=len(parents)):
+                return parents[int(g.integers(lo, hi))]
+            (C, NC) = pick(2, 3) if sep else pick()
+            (A, NA), (B, NB) = (pick(0, 2), pick(0, 2)) if sep else (pick(), pick())
+            m = int(g.integers(0, min(NC, NA) // div + 1))
+            n = int(g.integers(0, min(NC, NB) // div + 1))
+            k = int(g.integers(0, min(NA, NB) // div + 1))
+            items.append(dict(C=C, NC=NC, A=A, NA=NA, B=B, NB=NB,
+                              rc=int(g.integers(0, NC - m + 1)), cc=int(g.integers(0, NC - n + 1)),
+                              ra=int(g.integers(0, NA - m + 1)), ca=int(g.integers(0, NA - k + 1)),
+                              rb=int(g.integers(0, NB - k + 1)), cb=int(g.integers(0, NB - n + 1)),
+                              m=m, k=k, n=n))
+        descs = mh.make_descs(items)
+        got = mh.mh_validate_batch(descs, len(items), p, T, mh.MH_MODE_LIMB_I8)
+        want = mh.MH_E_ALIAS if _brute_alias(items) else mh.MH_OK
+        assert got == want, (trial, items)
+
+
+def test_validate_batch_errors():
+    item = dict(C=1 << 32, NC=1024, A=(1 << 32) + (8 << 20), NA=1024, B=(1 << 32) + (8 << 20),
+                NB=1024, rc=0, cc=0, ra=0, ca=0, rb=0, cb=0, m=64, k=64, n=64)
+    d = mh.make_descs([item])
+    assert mh.mh_validate_batch(d, 1, 65521, 64, mh.MH_MODE_LIMB_I8) == mh.MH_OK
+    assert mh.mh_validate_batch(d, 1, 2**31 + 1, 64, 2) == mh.MH_E_MODULUS
+    assert mh.mh_validate_batch(d, 1, 65521, 48, 2) == mh.MH_E_UNSUPPORTED
+    assert mh.mh_validate_batch(d, 1, 1 << 27, 64, mh.MH_MODE_FP64) == mh.MH_E_MODULUS
+    assert mh.mh_validate_batch(None, 1, 65521, 64, 2) == mh.MH_E_INVALID
+    bad = mh.make_descs([dict(item, rc=1000)])
+    assert mh.mh_validate_batch(bad, 1, 65521, 64, 2) == mh.MH_E_BOUNDS
+    two = mh.make_descs([item, dict(item, rc=32, cc=32)])
+    assert mh.mh_validate_batch(two, 2, 65521, 64, 2) == mh.MH_E_ALIAS
+    apart = mh.make_descs([item, dict(item, rc=64)])
+    assert mh.mh_validate_batch(apart, 2, 65521, 64, 2) == mh.MH_OK
