@@ -286,23 +286,32 @@ __global__ __launch_bounds__(256) void k_gemm_f64(PlainArgs a)
 
     // Tile (i, j), lane (lr, lg), element v: row 16 i + lg + 4 v, column 16 j + lr
     // (the result layout of v_mfma_f64_16x16x4f64).
+    // Per row group i, the C loads of its 16 outputs first, then the
+    // stores: in the other order each load would wait for the store before
+    // it (the compiler cannot tell the words apart).
     static_for<4>([&](auto i) {
+        auto rho_of = [&](int v) { return rho0 + wr * 64 + 16 * int(i) + lg + 4 * v; };
+        auto gam_of = [&](int j) { return gam0 + wc * 64 + 16 * j + lr; };
+        auto inside = [&](int v, int j) {
+            const int64_t rho = rho_of(v), gam = gam_of(j);
+            return rho >= a.sr && rho < a.sr + a.m && gam >= a.sc && gam < a.sc + a.n;
+        };
+        auto offset = [&](int v, int j) {
+            return mh_offset(uint64_t(a.row0C + rho_of(v)), uint64_t(a.col0C + gam_of(j)), a.logT);
+        };
+        uint32_t cv[4][4];
         static_for<4>([&](auto v) {
-            const int64_t rho = rho0 + wr * 64 + 16 * i + lg + 4 * v;
-            if (rho >= a.sr && rho < a.sr + a.m) {
-                static_for<4>([&](auto j) {
-                    const int64_t gam = gam0 + wc * 64 + 16 * j + lr;
-                    if (gam >= a.sc && gam < a.sc + a.n) {
-                        const uint32_t r = uint32_t(reduce_f64(acc[i][j][int(v)], pd, a.pinv));
-                        const uint64_t off = mh_offset(uint64_t(a.row0C + rho),
-                                                       uint64_t(a.col0C + gam), a.logT);
-                        const uint32_t add = a.sub ? (r ? a.p - r : 0u) : r;
-                        uint32_t c = a.C[off] + add;
-                        if (c >= a.p) c -= a.p;
-                        a.C[off] = c;
-                    }
-                });
-            }
+            static_for<4>([&](auto j) { cv[v][j] = inside(v, j) ? a.C[offset(v, j)] : 0u; });
+        });
+        static_for<4>([&](auto v) {
+            static_for<4>([&](auto j) {
+                if (!inside(v, j)) return;
+                const uint32_t r = uint32_t(reduce_f64(acc[i][j][int(v)], pd, a.pinv));
+                const uint32_t add = a.sub ? (r ? a.p - r : 0u) : r;
+                uint32_t c = cv[v][j] + add;
+                if (c >= a.p) c -= a.p;
+                a.C[offset(v, j)] = c;
+            });
         });
     });
 }

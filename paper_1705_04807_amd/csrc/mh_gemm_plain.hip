@@ -124,14 +124,27 @@ __global__ __launch_bounds__(256) void k_gemm_plain(PlainArgs a)
     // p = 2^31 - 1 (the prime of the large-prime workloads): 2^64 = 4 mod p
     // and shifts and adds replace the Barrett products.
     const bool mersenne = a.p == 0x7FFFFFFFu;
+    // Per output row, the C loads of its four words first, then the stores:
+    // in the other order each load would wait for the store before it (the
+    // compiler cannot tell the words apart).
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int64_t rho = rho0 + ty * 4 + i;
         if (rho < a.sr || rho >= a.sr + a.m) continue;
+        auto inside = [&](int j) {
+            const int64_t gam = gam0 + tx * 4 + j;
+            return gam >= a.sc && gam < a.sc + a.n;
+        };
+        auto offset = [&](int j) {
+            return mh_offset(uint64_t(a.row0C + rho), uint64_t(a.col0C + gam0 + tx * 4 + j),
+                             a.logT);
+        };
+        uint32_t cv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cv[j] = inside(j) ? a.C[offset(j)] : 0u;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int64_t gam = gam0 + tx * 4 + j;
-            if (gam < a.sc || gam >= a.sc + a.n) continue;
+            if (!inside(j)) continue;
             uint32_t r;
             if (mersenne) {
                 r = mod_m31(uint64_t(mod_m31(lo[i][j])) + (uint64_t(hi[i][j]) << 2));
@@ -139,11 +152,10 @@ __global__ __launch_bounds__(256) void k_gemm_plain(PlainArgs a)
                 const uint64_t hpart = uint64_t(mod_u64(hi[i][j], a.p, a.mu)) * r64;
                 r = mod_u64(uint64_t(mod_u64(lo[i][j], a.p, a.mu)) + hpart, a.p, a.mu);
             }
-            const uint64_t off = mh_offset(uint64_t(a.row0C + rho), uint64_t(a.col0C + gam), a.logT);
             const uint32_t add = a.sub ? (r ? a.p - r : 0u) : r;  // C - r = C + (p - r)
-            uint32_t c = a.C[off] + add;
+            uint32_t c = cv[j] + add;
             if (c >= a.p) c -= a.p;
-            a.C[off] = c;
+            a.C[offset(j)] = c;
         }
     }
 }
