@@ -106,12 +106,13 @@ mh_status ensure_queue(mh_ctx *ctx, int64_t ncalls)
     return MH_OK;
 }
 
-// Capture reset -> pack -> GEMM for kernel configuration cfg and L limbs,
-// once per context, queue buffer and (cfg, L); returns the executable graph.
-hipGraphExec_t ensure_graph(mh_ctx *ctx, int cfg, int L)
+// Capture reset -> pack -> GEMM for kernel configuration cfg, L limbs and
+// the GEMM's C-load form, once per context, queue buffer and (cfg, L, form);
+// returns the executable graph.
+hipGraphExec_t ensure_graph(mh_ctx *ctx, int cfg, int L, bool early_c)
 {
     BatchedState &b = ctx->batched;
-    const int key = cfg * 8 + L;
+    const int key = (cfg * 8 + L) * 2 + (early_c ? 1 : 0);
     auto it = b.graphs.find(key);
     if (it != b.graphs.end()) return it->second.exec;
     const QueueView q = queue_view(b.queue_dev, b.queue_cap);
@@ -120,7 +121,7 @@ hipGraphExec_t ensure_graph(mh_ctx *ctx, int cfg, int L)
         return nullptr;
     hipError_t e1 = launch_reset_counters(b.counters, cs);
     hipError_t e2 = launch_pack_limb_batched(L, q, b.counters, ctx->num_cu, cs);
-    hipError_t e3 = launch_gemm_limb_batched(cfg, L, q, b.counters + 2, ctx->num_cu, cs);
+    hipError_t e3 = launch_gemm_limb_batched(cfg, L, early_c, q, b.counters + 2, ctx->num_cu, cs);
     hipGraph_t g = nullptr;
     hipError_t e4 = hipStreamEndCapture(cs, &g);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || !g) {
@@ -238,6 +239,7 @@ namespace mh {
 mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int L, uint32_t p,
                        hipStream_t stream, uint32_t *c_override)
 {
+    if (plans.empty()) return MH_OK;
     // Longest-processing-time order: every output block of a product costs
     // its k, so products with the longest k go first.  In that order each
     // product joins the XCD group with the least work so far (blocks x k);
@@ -340,7 +342,7 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
         first_call += group_calls[g];
     }
 
-    hipGraphExec_t exec = ensure_graph(ctx, cfg, L);
+    hipGraphExec_t exec = ensure_graph(ctx, cfg, L, limb_batched_early_c(plans[0].pr.logT));
     if (!exec) return MH_E_DEVICE;
     hipError_t e = hipMemcpyAsync(b.queue_dev, b.queue_host, queue_bytes(b.queue_cap),
                                   hipMemcpyHostToDevice, stream);

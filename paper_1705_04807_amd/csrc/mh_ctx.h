@@ -25,8 +25,9 @@ struct BatchedState {
     hipEvent_t staging_free = nullptr;  // recorded after the last host-to-device queue copy
     uint64_t *counters = nullptr;       // device work counters (pack, GEMM)
     hipStream_t capture_stream = nullptr;
-    // One captured graph per (kernel configuration, limbs): a batch whose
-    // configuration differs from the previous one's replays its own graph, so
+    // One captured graph per (kernel configuration, limbs, C-load form of
+    // the GEMM): a batch whose key differs from the previous one's replays
+    // its own graph, so
     // no graph is destroyed while a launch of it may still run.  All of them
     // embed the queue's address and are destroyed together when the queue
     // is reallocated (after the context's work has drained).

@@ -25,19 +25,31 @@ namespace mh {
 
 namespace {
 
+// C through a global-address-space pointer: its loads and stores are then
+// global (vector memory counter only) rather than flat, which the compiler
+// also counts as LDS accesses, so that every wait for a fragment read from
+// LDS would wait for the C traffic as well.
+typedef __attribute__((address_space(1))) uint32_t gu32;
+
+// Stages between the early C loads and the epilogue (persistent kernel, one
+// 32 x 32 block per wave, L <= 2).
+constexpr int kCLead = 2;
+
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 // One workgroup's output block (gm, gn) of the product described by `a`.
 // PIPE (LDS path): fragment reads one k-block ahead of the MFMAs, with a
 // second fragment set.
-template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF, bool PIPE>
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF, bool PIPE,
+          bool EARLYC = false>
 __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t gn)
 {
     constexpr int S = 2 * L - 1;
     constexpr int BM = 32 * WM * WAVES_M, BN = 32 * WN * WAVES_N;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wmi = wave / WAVES_N, wni = wave % WAVES_N;
+    gu32 *const Cg = (gu32 *)a.C;
 
     const int64_t slabA = gm * (WM * WAVES_M) + wmi * WM;
     const int64_t slabB = gn * (WN * WAVES_N) + wni * WN;
@@ -51,6 +63,57 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
     static_for<S>([&](auto s) {
         static_for<WM>([&](auto i) { static_for<WN>([&](auto j) { acc[s][i][j] = v16i{0}; }); });
     });
+
+    // C words of the wave's outputs loaded kCLead stages ahead of the
+    // epilogue (one 32 x 32 block per wave, at L <= 2 in the persistent
+    // kernel: a block there is a short pipeline, and its C round trip would
+    // otherwise stall the waves between two blocks).  The panel shifts start
+    // the wave's block on multiples of min(T, 32) in C's rows and columns,
+    // so for 32 <= T <= 2^14 (the launch selects this form only then) it
+    // lies inside one T x T tile: one base per wave and 32-bit byte offsets
+    // per output keep the 16 loads within a few registers.  A wave whose block lies wholly outside the output
+    // block reads C(rc, cc) instead, and out-of-block outputs read (and
+    // discard) words of their valid tile, so every wave issues all 16
+    // loads, without branches, and the stage waits can count them.
+    constexpr bool kEarlyC = EARLYC && LDS && !PIPE && WM * WN == 1;
+    uint32_t cpre[16];
+    auto c_tile = [&](auto &&f) {
+        // f(v, inside, base, byte offset) for the lane's 16 outputs
+        const uint32_t tmask = (1u << a.logT) - 1;
+        const int wu = __builtin_amdgcn_readfirstlane(wave);  // (wave-uniform: scalar)
+        const int64_t rho0 = gm * BM + (wu / WAVES_N) * 32, gam0 = gn * BN + (wu % WAVES_N) * 32;
+        const bool any = rho0 < a.sr + a.m && rho0 + 32 > a.sr && gam0 < a.sc + a.n &&
+                         gam0 + 32 > a.sc;
+        // (a wave outside the block reads the 32-aligned 32 x 32 block
+        // around C(rc, cc), inside that word's tile)
+        const uint32_t R0 = any ? uint32_t(a.row0C + rho0) : uint32_t(a.row0C + a.sr) & ~31u;
+        const uint32_t C0 = any ? uint32_t(a.col0C + gam0) : uint32_t(a.col0C + a.sc) & ~31u;
+        const uint64_t tile = uint64_t((spread16(R0 >> a.logT) << 1) | spread16(C0 >> a.logT))
+                              << (2 * a.logT);
+        gu32 *const base = Cg + tile;
+        uint32_t off = ((((R0 & tmask) + uint32_t((lane >> 5) * 4)) << a.logT) + (C0 & tmask) +
+                        uint32_t(lane & 31))
+                       << 2;
+        // (computed where used: hoisted out of the k loop, the addresses
+        // would hold registers through it)
+        asm volatile("" : "+v"(off));
+        const int64_t gam = gam0 + (lane & 31);
+        const bool col_in = any && gam >= a.sc && gam < a.sc + a.n;
+        static_for<16>([&](auto v) {
+            constexpr int drow = (int(v) >> 2) * 8 + (int(v) & 3);
+            const int64_t rho = rho0 + drow + (lane >> 5) * 4;
+            const bool in = col_in && rho >= a.sr && rho < a.sr + a.m;
+            f(v, in, base, off + (uint32_t(drow) << (a.logT + 2)));
+        });
+    };
+    auto word = [](gu32 *base, uint32_t byte_off) -> gu32 & {
+        return *(gu32 *)((__attribute__((address_space(1))) char *)base + byte_off);
+    };
+    auto fetch_c = [&]() {
+        if constexpr (kEarlyC) {
+                c_tile([&](auto v, bool, gu32 *base, uint32_t off) { cpre[int(v)] = word(base, off); });
+        }
+    };
 
     // Combine the shift accumulators of one k-block by Horner into residues
     // (highest shift first: r <- 256 r + T_s mod p, so each shift's registers
@@ -72,10 +135,32 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
             r = r >= pd ? r - pd : r;
             return r;
         };
-        double r[WM][WN][16];
         // Three shifts (L = 2) need one reduction: 65536 T_2 + 256 T_1 + T_0
         // is below 2^48 in magnitude as well.
         constexpr int S0 = S == 3 ? 3 : 1;  // shifts taken by the first reduction
+        if constexpr (kEarlyC) {
+            // One output at a time, from its accumulators to its early C word.
+            c_tile([&](auto v, bool in, gu32 *base, uint32_t off) {
+                double x = double(acc[S - 1][0][0][int(v)]);
+                if constexpr (S0 == 3)
+                    x = fma(x, 65536.0, fma(double(acc[1][0][0][int(v)]), 256.0,
+                                            double(acc[0][0][0][int(v)])));
+                double rv = red(x);
+                static_for<(S - S0) / 2>([&](auto q) {
+                    constexpr int hi = S - 2 - 2 * q, lo = hi - 1;
+                    rv = red(fma(rv, 65536.0, fma(double(acc[hi][0][0][int(v)]), 256.0,
+                                                  double(acc[lo][0][0][int(v)]))));
+                });
+                if (in) {
+                    uint32_t c = cpre[int(v)] + uint32_t(rv);
+                    if (c >= a.p) c -= a.p;
+                    word(base, off) = c;
+                }
+            });
+            static_for<S>([&](auto t) { acc[t][0][0] = v16i{0}; });
+            return;
+        }
+        double r[WM][WN][16];
         static_for<WM>([&](auto i) {
             static_for<WN>([&](auto j) {
                 static_for<16>([&](auto v) {
@@ -138,14 +223,14 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
                         uint32_t cv[8];
                         static_for<8>([&](auto u) {
                             constexpr int v = int(h) * 8 + int(u);
-                            cv[u] = inside(v) ? a.C[offset(v)] : 0u;
+                            cv[u] = inside(v) ? Cg[offset(v)] : 0u;
                         });
                         static_for<8>([&](auto u) {
                             constexpr int v = int(h) * 8 + int(u);
                             if (!inside(v)) return;
                             uint32_t c = cv[u] + uint32_t(r[i][j][v]);
                             if (c >= a.p) c -= a.p;
-                            a.C[offset(v)] = c;
+                            Cg[offset(v)] = c;
                         });
                     });
                 } else {
@@ -158,9 +243,9 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
                         const uint32_t tile = rowbits[v >= 8 ? 1 : 0] | colbits;
                         const uint64_t off = (uint64_t(tile) << (2 * a.logT)) |
                                              ((rowC & tmask) << a.logT) | colin;
-                        uint32_t c = a.C[off] + uint32_t(r[i][j][v]);
+                        uint32_t c = Cg[off] + uint32_t(r[i][j][v]);
                         if (c >= a.p) c -= a.p;
-                        a.C[off] = c;
+                        Cg[off] = c;
                     });
                 }
             });
@@ -275,6 +360,7 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
         constexpr int kWaitInFlight = ((NBUF - 2) * RMIN & 15) | (7 << 4) |
                                       (((NBUF - 2) * RMIN >> 4) << 14);
         constexpr int kWaitAll = 7 << 4;  // vmcnt(0) lgkmcnt(0)
+        constexpr int kWaitC = (1 << 14) | (7 << 4);  // vmcnt(16) lgkmcnt(0): the early C loads
         static_assert(KS % 2 == 0, "fragment sets alternate within and across stages");
         const int64_t nst = nkb / KS, st_red = a.kb_per_red / KS;
 
@@ -288,9 +374,11 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
         // barrier: the fence of __syncthreads() would make the compiler wait
         // for the later stages' loads as well.  The empty asm statements keep
         // memory accesses on their side.
-        auto enter_stage = [&](int64_t s, bool after_epilogue) {
+        auto enter_stage = [&](int64_t s, bool after_epilogue, bool c_pending = false) {
             if (NBUF > 2 && s + NBUF - 2 < nst && !after_epilogue)
                 __builtin_amdgcn_s_waitcnt(kWaitInFlight);
+            else if (c_pending)
+                __builtin_amdgcn_s_waitcnt(kWaitC);
             else
                 __builtin_amdgcn_s_waitcnt(kWaitAll);
             asm volatile("" ::: "memory");
@@ -362,14 +450,34 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
             // One fragment set, read right before its MFMAs.
             for (int64_t st0 = 0; st0 < nst; st0 += st_red) {
                 const int64_t st1 = (st0 + st_red < nst) ? st0 + st_red : nst;
-                for (int64_t st = st0; st < st1; ++st) {
-                    enter_stage(st, st == st0 && st0 > 0);
+                // The early C loads go out with the first k-block of stage
+                // st_c, after the loads of stage st_c + 1: entering that
+                // stage waits for all but those 16 loads (loads complete in
+                // order), so their latency hides behind whole stages.
+                // (Stage st_c comes after the loop: inside it, the loads'
+                // registers would look busy on the loop's back edge, and the
+                // compiler would wait for all loads before reusing them.)
+                const int64_t st_c = st1 - kCLead > st0 ? st1 - kCLead : st0;
+                auto body = [&](int64_t st, bool fetch) {
                     static_for<KS>([&](auto q) {
                         FragA1 fa;
                         FragB1 fb;
                         read(fa, fb, st, int(q));
+                        if (int(q) == 0 && fetch) fetch_c();
                         mma1(fa, fb);
                     });
+                };
+                for (int64_t st = st0; st < (kEarlyC ? st_c : st1); ++st) {
+                    enter_stage(st, st == st0 && st0 > 0);
+                    body(st, false);
+                }
+                if constexpr (kEarlyC) {
+                    enter_stage(st_c, st_c == st0 && st0 > 0);
+                    body(st_c, true);
+                    for (int64_t st = st_c + 1; st < st1; ++st) {
+                        enter_stage(st, false, st == st_c + 1);
+                        body(st, false);
+                    }
                 }
                 flush();
             }
@@ -401,7 +509,7 @@ k_gemm_limb(LimbArgs a)
 // the next block is issued when a block starts and read when it ends, so
 // its latency hides behind the block.  A forward search over the per-call
 // prefix sums finds the call of a block.
-template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF>
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF, bool EARLYC>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N,
                              (WAVES_M * WAVES_N == 8 && WM * WN == 1 && L <= 2) ? 4 : 1) void
 k_gemm_limb_batched(
@@ -446,8 +554,8 @@ k_gemm_limb_batched(
             // that two workgroups share a compute unit and one's epilogue
             // and first loads overlap the other's MFMAs.
             constexpr bool kPipe = WAVES_M * WAVES_N <= 8 && WM * WN == 1 && L > 2;
-            gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, kPipe>(a, local / a.grid_n,
-                                                                        local % a.grid_n);
+            gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, kPipe, EARLYC>(
+                a, local / a.grid_n, local % a.grid_n);
             cur = publish(next);
         }
     }
@@ -509,17 +617,24 @@ bool cfg_fits(int L, const LimbKernelCfg &c)
 }
 
 template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF = 2>
-hipError_t launch_batched_one(const QueueView &q, uint64_t *counters, int num_cu, hipStream_t s)
+hipError_t launch_batched_one(bool early_c, const QueueView &q, uint64_t *counters, int num_cu,
+                              hipStream_t s)
 {
-    auto kern = k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>;
+    // The early-C form exists where the kernel multiplies without a second
+    // fragment set, one 32 x 32 block per wave.
+    constexpr bool kCan = LDS && WM * WN == 1 && L <= 2;
+    auto kern = k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, false>;
+    if constexpr (kCan) {
+        if (early_c) kern = k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, true>;
+    }
     const size_t shm = lds_bytes<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>();
     if (shm > 65536) {
-        static bool set = false;
-        if (!set && hipFuncSetAttribute((const void *)kern,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        int(shm)) != hipSuccess)
+        static bool set[2] = {false, false};
+        if (!set[early_c && kCan] &&
+            hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                int(shm)) != hipSuccess)
             return hipErrorInvalidValue;
-        set = true;
+        set[early_c && kCan] = true;
     }
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * WAVES_M * WAVES_N, shm) !=
@@ -531,38 +646,38 @@ hipError_t launch_batched_one(const QueueView &q, uint64_t *counters, int num_cu
 }
 
 template <int L>
-hipError_t dispatch_batched_L(int cfg, const QueueView &q, uint64_t *counters, int num_cu,
-                              hipStream_t s)
+hipError_t dispatch_batched_L(int cfg, bool early_c, const QueueView &q, uint64_t *counters,
+                              int num_cu, hipStream_t s)
 {
     switch (cfg) {
-    case 0: return launch_batched_one<L, 1, 2, 2, 2, 1, false>(q, counters, num_cu, s);
-    case 1: return launch_batched_one<L, 1, 1, 2, 2, 1, false>(q, counters, num_cu, s);
-    case 2: return launch_batched_one<L, 2, 1, 2, 2, 1, false>(q, counters, num_cu, s);
+    case 0: return launch_batched_one<L, 1, 2, 2, 2, 1, false>(early_c, q, counters, num_cu, s);
+    case 1: return launch_batched_one<L, 1, 1, 2, 2, 1, false>(early_c, q, counters, num_cu, s);
+    case 2: return launch_batched_one<L, 2, 1, 2, 2, 1, false>(early_c, q, counters, num_cu, s);
     case 3:
-        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 1, false>(q, counters, num_cu, s);
+        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 1, false>(early_c, q, counters, num_cu, s);
         return hipErrorInvalidValue;
-    case 4: return launch_batched_one<L, 1, 2, 2, 2, 2, false>(q, counters, num_cu, s);
+    case 4: return launch_batched_one<L, 1, 2, 2, 2, 2, false>(early_c, q, counters, num_cu, s);
     case 5:
-        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 2, false>(q, counters, num_cu, s);
+        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 2, false>(early_c, q, counters, num_cu, s);
         return hipErrorInvalidValue;
-    case 6: return launch_batched_one<L, 1, 1, 2, 2, 2, false>(q, counters, num_cu, s);
-    case 7: return launch_batched_one<L, 1, 2, 2, 2, 2, true>(q, counters, num_cu, s);
+    case 6: return launch_batched_one<L, 1, 1, 2, 2, 2, false>(early_c, q, counters, num_cu, s);
+    case 7: return launch_batched_one<L, 1, 2, 2, 2, 2, true>(early_c, q, counters, num_cu, s);
     case 8:
-        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 2, true>(q, counters, num_cu, s);
+        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 2, true>(early_c, q, counters, num_cu, s);
         return hipErrorInvalidValue;
-    case 9: return launch_batched_one<L, 1, 1, 2, 2, 2, true>(q, counters, num_cu, s);
-    case 10: return launch_batched_one<L, 2, 1, 2, 2, 2, true>(q, counters, num_cu, s);
-    case 11: return launch_batched_one<L, 1, 1, 2, 4, 2, true>(q, counters, num_cu, s);
-    case 12: return launch_batched_one<L, 1, 1, 4, 2, 2, true>(q, counters, num_cu, s);
+    case 9: return launch_batched_one<L, 1, 1, 2, 2, 2, true>(early_c, q, counters, num_cu, s);
+    case 10: return launch_batched_one<L, 2, 1, 2, 2, 2, true>(early_c, q, counters, num_cu, s);
+    case 11: return launch_batched_one<L, 1, 1, 2, 4, 2, true>(early_c, q, counters, num_cu, s);
+    case 12: return launch_batched_one<L, 1, 1, 4, 2, 2, true>(early_c, q, counters, num_cu, s);
     case 13:
-        if constexpr (L <= 2) return launch_batched_one<L, 1, 1, 4, 4, 2, true>(q, counters, num_cu, s);
+        if constexpr (L <= 2) return launch_batched_one<L, 1, 1, 4, 4, 2, true>(early_c, q, counters, num_cu, s);
         return hipErrorInvalidValue;
     case 14:
         if constexpr (L <= 2)
-            return launch_batched_one<L, 1, 1, 4, 4, 2, true, 3>(q, counters, num_cu, s);
+            return launch_batched_one<L, 1, 1, 4, 4, 2, true, 3>(early_c, q, counters, num_cu, s);
         return hipErrorInvalidValue;
     case 15:
-        if constexpr (L <= 2) return launch_batched_one<L, 1, 2, 4, 2, 2, true>(q, counters, num_cu, s);
+        if constexpr (L <= 2) return launch_batched_one<L, 1, 2, 4, 2, 2, true>(early_c, q, counters, num_cu, s);
         return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
@@ -623,15 +738,17 @@ int limb_cfg_default(int L, int64_t m, int64_t n, int64_t k)
     return L <= 2 ? 11 : 9;
 }
 
-hipError_t launch_gemm_limb_batched(int cfg, int L, const QueueView &q, uint64_t *counters,
-                                    int num_cu, hipStream_t s)
+bool limb_batched_early_c(int logT) { return logT >= 5 && logT <= 14; }
+
+hipError_t launch_gemm_limb_batched(int cfg, int L, bool early_c, const QueueView &q,
+                                    uint64_t *counters, int num_cu, hipStream_t s)
 {
     if (cfg < 0 || cfg >= limb_cfg_count() || !cfg_fits(L, kCfgs[cfg])) return hipErrorInvalidValue;
     switch (L) {
-    case 1: return dispatch_batched_L<1>(cfg, q, counters, num_cu, s);
-    case 2: return dispatch_batched_L<2>(cfg, q, counters, num_cu, s);
-    case 3: return dispatch_batched_L<3>(cfg, q, counters, num_cu, s);
-    case 4: return dispatch_batched_L<4>(cfg, q, counters, num_cu, s);
+    case 1: return dispatch_batched_L<1>(cfg, early_c, q, counters, num_cu, s);
+    case 2: return dispatch_batched_L<2>(cfg, early_c, q, counters, num_cu, s);
+    case 3: return dispatch_batched_L<3>(cfg, false, q, counters, num_cu, s);
+    case 4: return dispatch_batched_L<4>(cfg, false, q, counters, num_cu, s);
     }
     return hipErrorInvalidValue;
 }

@@ -335,8 +335,11 @@ inline QueueView queue_view(void *base, int64_t cap)
 constexpr int kBatchCounters = 2 + kXcdGroups;
 hipError_t launch_pack_limb_batched(int L, const QueueView &q, uint64_t *counters, int num_cu,
                                     hipStream_t s);
-hipError_t launch_gemm_limb_batched(int cfg, int L, const QueueView &q, uint64_t *counters,
-                                    int num_cu, hipStream_t s);
+// early_c: the form that loads C ahead of the epilogue (valid when
+// limb_batched_early_c(logT) holds for the batch's tile size).
+bool limb_batched_early_c(int logT);
+hipError_t launch_gemm_limb_batched(int cfg, int L, bool early_c, const QueueView &q,
+                                    uint64_t *counters, int num_cu, hipStream_t s);
 hipError_t launch_reset_counters(uint64_t *counters, hipStream_t s);
 
 }  // namespace mh

@@ -77,6 +77,29 @@ def test_batched_random(mh, ctx, mode, p, T):
     run_batch(mh, ctx, calls, A, B, Cs, Ad, Bd, Cds, NA, NB, NC, p, T, mode)
 
 
+@pytest.mark.parametrize("p,T", [(65521, 32), (65521, 128), (251, 64), (251, 32)])
+def test_batched_early_c_forms(mh, ctx, p, T):
+    """The persistent GEMM form that loads C two stages ahead of the epilogue
+    (one and two limbs, 32 <= T): tile sizes other than 64, and thin products
+    whose output blocks leave whole waves of a workgroup outside them (those
+    waves load words they discard and store nothing)."""
+    g = np.random.default_rng(950 + T + p % 97)
+    NA = NB = NC = 1024
+    nC = 3
+    A, B = parent_host(951, p, NA), parent_host(952, p, NB)
+    Cs = [parent_host(960 + i, p, NC) for i in range(nC)]
+    Ad, Bd = to_mh(mh, ctx, device_of(A), NA, T), to_mh(mh, ctx, device_of(B), NB, T)
+    Cds = [to_mh(mh, ctx, device_of(C), NC, T) for C in Cs]
+    calls = [c for c in draw_batch(g, 24, NA, NB, NC, nC, 300) if c["ci"] < 2]
+    for i in range(6):  # thin blocks in parent 2, rows disjoint
+        m, k, n = 1 + 7 * i, 33 + 50 * i, 100 + 37 * i
+        calls.append(dict(ci=2, rc=5 + 150 * i, cc=17 + 3 * i, m=m, k=k, n=n,
+                          ra=int(g.integers(0, NA - m + 1)), ca=int(g.integers(0, NA - k + 1)),
+                          rb=int(g.integers(0, NB - k + 1)), cb=int(g.integers(0, NB - n + 1))))
+    say("batched early C", p, T, len(calls))
+    run_batch(mh, ctx, calls, A, B, Cs, Ad, Bd, Cds, NA, NB, NC, p, T, 2)
+
+
 def test_batched_graph_replay_new_queue(mh, ctx):
     # one captured graph, three batches with different contents and sizes
     p, T = 65521, 64
