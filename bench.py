@@ -580,11 +580,11 @@ def batched_workload(args, mh, steps, warmup, cpu_budget):
         batched(mh.MH_MODE_LIMB_I8)
     t_b, ks = timed(lambda: batched(mh.MH_MODE_LIMB_I8), steps, (mh.MH_K_BATCHED,))
     graph_ms = ks[mh.MH_K_BATCHED][0] / max(ks[mh.MH_K_BATCHED][1], 1)
-    s, batch_cfg, L = mh.mh_ctx_last_batch_config(ctx)
+    s, batch_cfg, L, forms = mh.mh_ctx_last_batch_config(ctx)
     mh.check(s)
     value = work / t_b / 1e9
-    log("batched: %.3f ms/step (graph %.3f ms, configuration %d)" % (t_b * 1e3, graph_ms,
-                                                                      batch_cfg))
+    log("batched: %.3f ms/step (graph %.3f ms, configuration %d, forms %d)"
+        % (t_b * 1e3, graph_ms, batch_cfg, forms))
     looped(mh.MH_MODE_LIMB_I8)
     t_l, _ = timed(lambda: looped(mh.MH_MODE_LIMB_I8), 2)
     log("batched: looped %.3f ms" % (t_l * 1e3))
@@ -620,6 +620,8 @@ def batched_workload(args, mh, steps, warmup, cpu_budget):
                      "traffic": recorded_traffic("batched_graph", batch_cfg, BATCHED, src),
                      "kernel": "batched graph (k_pack_limb_batched + k_gemm_limb_batched)",
                      "kernel_cfg": batch_cfg, "kernel_src": src, "kernel_ms": graph_ms,
+                     "kernel_forms": {"early_c": bool(forms & mh.MH_BATCH_FORM_EARLY_C),
+                                      "a_parent": bool(forms & mh.MH_BATCH_FORM_A_PARENT)},
                      "note": "achieved = int8 multiply-add operations of the whole batch "
                              "(L^2 * sum 2mnk) / graph time, in tera-operations per second; "
                              "traffic = HBM bytes per graph launch (both pack kernels and the "

@@ -361,10 +361,15 @@ mh_status mh_validate_batch(const mh_mm_desc *descs, int32_t count, uint32_t p, 
                             int32_t mode);
 
 /* Kernel configuration (index into the limb kernel table, as reported by
- * mh_plan_info.kernel_cfg) and limb count of the last batched graph the
- * context launched for a caller (tuning runs excluded); -1 and 0 if none.
- * Either pointer may be null. */
-mh_status mh_ctx_last_batch_config(mh_ctx *ctx, int32_t *cfg, int32_t *limbs);
+ * mh_plan_info.kernel_cfg), limb count and GEMM forms of the last batched
+ * graph the context launched for a caller (tuning runs excluded); -1, 0 and
+ * 0 if none.  forms: MH_BATCH_FORM_EARLY_C if the GEMM loaded C ahead of its
+ * epilogue, MH_BATCH_FORM_A_PARENT if it read A from panels of whole
+ * parents (each A parent packed once for the batch).  Any pointer may be
+ * null. */
+#define MH_BATCH_FORM_EARLY_C 1
+#define MH_BATCH_FORM_A_PARENT 2
+mh_status mh_ctx_last_batch_config(mh_ctx *ctx, int32_t *cfg, int32_t *limbs, int32_t *forms);
 
 /* ------------------------------------------------------ planner, host only */
 

@@ -53,6 +53,9 @@ MH_K_BATCHED = 5
 MH_K_GEMM_F64 = 6
 MH_K_COUNT = 7
 
+MH_BATCH_FORM_EARLY_C = 1  # mh_ctx_last_batch_config forms
+MH_BATCH_FORM_A_PARENT = 2
+
 # Every symbol declared in include/mh.h.
 EXPORTS = (
     "mh_ctx_create", "mh_ctx_destroy", "mh_status_string", "mh_ctx_last_device_error",
@@ -134,7 +137,8 @@ def _load():
         "mh_matmul_modp_noalloc": ([P, P, I64, I64, I64, P, I64, I64, I64, P, I64, I64, I64, I64,
                                     I64, I64, U32, I32, I32, P], ct.c_int),
         "mh_matmul_modp_batched": ([P, ct.POINTER(mh_mm_desc), I32, U32, I32, I32, P], ct.c_int),
-        "mh_ctx_last_batch_config": ([P, ct.POINTER(I32), ct.POINTER(I32)], ct.c_int),
+        "mh_ctx_last_batch_config": ([P, ct.POINTER(I32), ct.POINTER(I32), ct.POINTER(I32)],
+                                     ct.c_int),
         "mh_validate_batch": ([ct.POINTER(mh_mm_desc), I32, U32, I32, I32], ct.c_int),
         "mh_plan_describe": ([I64] * 12 + [U32, I32, I32, ct.POINTER(mh_plan_info)], ct.c_int),
         "mh_plan_leaves": ([I64] * 12 + [I32, ct.POINTER(I64), I64, ct.POINTER(I64)], ct.c_int),
@@ -326,11 +330,11 @@ def mh_validate_batch(descs, count: int, p: int, T: int, mode: int = MH_MODE_AUT
     return lib.mh_validate_batch(descs, count, p, T, mode)
 
 
-def mh_ctx_last_batch_config(ctx) -> tuple[int, int, int]:
-    """(status, cfg, limbs) of the last batched graph the context launched."""
-    cfg, limbs = ct.c_int32(-1), ct.c_int32(0)
-    s = lib.mh_ctx_last_batch_config(ctx, ct.byref(cfg), ct.byref(limbs))
-    return s, cfg.value, limbs.value
+def mh_ctx_last_batch_config(ctx) -> tuple[int, int, int, int]:
+    """(status, cfg, limbs, forms) of the last batched graph the context launched."""
+    cfg, limbs, forms = ct.c_int32(-1), ct.c_int32(0), ct.c_int32(0)
+    s = lib.mh_ctx_last_batch_config(ctx, ct.byref(cfg), ct.byref(limbs), ct.byref(forms))
+    return s, cfg.value, limbs.value, forms.value
 
 
 def mh_plan_describe(NC, rc, cc, NA, ra, ca, NB, rb, cb, m, k, n, p, T, mode=MH_MODE_AUTO):

@@ -107,12 +107,12 @@ mh_status ensure_queue(mh_ctx *ctx, int64_t ncalls)
 }
 
 // Capture reset -> pack -> GEMM for kernel configuration cfg, L limbs and
-// the GEMM's C-load form, once per context, queue buffer and (cfg, L, form);
-// returns the executable graph.
-hipGraphExec_t ensure_graph(mh_ctx *ctx, int cfg, int L, bool early_c)
+// the GEMM's forms (C loaded early, A from whole-parent panels), once per
+// context, queue buffer and key; returns the executable graph.
+hipGraphExec_t ensure_graph(mh_ctx *ctx, int cfg, int L, bool early_c, bool a_parent)
 {
     BatchedState &b = ctx->batched;
-    const int key = (cfg * 8 + L) * 2 + (early_c ? 1 : 0);
+    const int key = ((cfg * 8 + L) * 2 + (early_c ? 1 : 0)) * 2 + (a_parent ? 1 : 0);
     auto it = b.graphs.find(key);
     if (it != b.graphs.end()) return it->second.exec;
     const QueueView q = queue_view(b.queue_dev, b.queue_cap);
@@ -121,7 +121,8 @@ hipGraphExec_t ensure_graph(mh_ctx *ctx, int cfg, int L, bool early_c)
         return nullptr;
     hipError_t e1 = launch_reset_counters(b.counters, cs);
     hipError_t e2 = launch_pack_limb_batched(L, q, b.counters, ctx->num_cu, cs);
-    hipError_t e3 = launch_gemm_limb_batched(cfg, L, early_c, q, b.counters + 2, ctx->num_cu, cs);
+    hipError_t e3 =
+        launch_gemm_limb_batched(cfg, L, early_c, a_parent, q, b.counters + 2, ctx->num_cu, cs);
     hipGraph_t g = nullptr;
     hipError_t e4 = hipStreamEndCapture(cs, &g);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || !g) {
@@ -264,14 +265,71 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
     std::stable_sort(order.begin(), order.end(),
                      [&](size_t a, size_t b) { return grp[a] < grp[b]; });
 
-    // Panels of every product in the context workspace.
+    // A operands from whole-parent panels: each distinct A parent is packed
+    // once, and the GEMM reads every product's A block out of its parent's
+    // panel (a TU level's products are blocks of a few shared parents, each
+    // word of which lies in many products' A blocks).  Chosen when the A
+    // blocks hold at least as many words as their parents (MH_BATCH_APARENT
+    // = 0 never, 1 whenever the configuration has that form), and every
+    // parent panel stays below 2 GiB.  B's panels then start their depth at
+    // the phase ca mod 32 of A's columns in the parent's k-blocks.
+    struct AParent {
+        const uint32_t *A;
+        int64_t N, nslab, nkbp;
+        size_t off;
+    };
+    std::vector<AParent> apars;
+    std::vector<int> apar_of(plans.size(), -1);
+    bool a_parent = limb_batched_a_parent(cfg, L);
+    if (a_parent) {
+        const char *env = std::getenv("MH_BATCH_APARENT");
+        const int want = env ? std::atoi(env) : -1;
+        double words = 0.0, pwords = 0.0;
+        for (size_t q = 0; q < plans.size() && a_parent; ++q) {
+            const Product &pr = plans[q].pr;
+            words += double(pr.m) * double(pr.k);
+            int idx = -1;
+            for (size_t u = 0; u < apars.size(); ++u)
+                if (apars[u].A == pr.A && apars[u].N == pr.NA) idx = int(u);
+            if (idx < 0) {
+                AParent ap;
+                ap.A = pr.A;
+                ap.N = pr.NA;
+                ap.nslab = (pr.NA + 63) / 64 * 2;  // rows in whole 64-row pack chunks
+                ap.nkbp = (pr.NA + 63) / 64 * 2;   // an even number of k-blocks
+                ap.off = 0;
+                if ((ap.nslab + 2 * kAParentGuard) * ap.nkbp * L * 1024 >= (int64_t(1) << 31))
+                    a_parent = false;
+                pwords += double(pr.NA) * double(pr.NA);
+                apars.push_back(ap);
+                idx = int(apars.size()) - 1;
+            }
+            apar_of[q] = idx;
+        }
+        a_parent = a_parent && want != 0 && (want == 1 || words >= pwords);
+    }
+    // GEMM k-blocks of each product (A-parent form: from the phase of ca)
+    std::vector<int64_t> nkbs(plans.size());
+    for (size_t q = 0; q < plans.size(); ++q) {
+        const Product &pr = plans[q].pr;
+        nkbs[q] = a_parent ? (pr.ca % 32 + pr.k + 63) / 64 * 2 : plans[q].kpad / 32;
+    }
+
+    // Panels in the context workspace: the parents' (A-parent form), then
+    // every product's own.
     std::vector<size_t> aoff(plans.size()), boff(plans.size());
     size_t total = 0;
+    if (a_parent)
+        for (AParent &ap : apars) {
+            const size_t slab = size_t(ap.nkbp) * size_t(L) * 1024;
+            ap.off = total + size_t(kAParentGuard) * slab;
+            total += align256((size_t(ap.nslab) + 2 * size_t(kAParentGuard)) * slab);
+        }
     for (size_t q = 0; q < plans.size(); ++q) {
         const Plan &pl = plans[q];
-        const size_t nkb = size_t(pl.kpad / 32);
-        aoff[q] = total;
-        total += align256(size_t(pl.prow) * nkb * 32 * L);
+        const size_t nkb = size_t(nkbs[q]);
+        aoff[q] = a_parent ? apars[apar_of[q]].off : total;
+        if (!a_parent) total += align256(size_t(pl.prow) * nkb * 32 * L);
         boff[q] = total;
         total += align256(size_t(pl.pcol) * nkb * 32 * L);
     }
@@ -289,14 +347,23 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
     for (int64_t q = 0; q < ncalls; ++q) {
         const Plan &pl = plans[order[q]];
         const Product &pr = pl.pr;
-        const int64_t nkb = pl.kpad / 32;
+        const int64_t nkb = nkbs[order[q]];
         int8_t *Ap = (int8_t *)(ws + aoff[order[q]]);
         int8_t *Bp = (int8_t *)(ws + boff[order[q]]);
-        // A panels are tasks [0, ncalls), B panels [ncalls, 2 ncalls)
-        hq.packs[q] =
-            PackTask{pr.A, Ap, pr.ra, pr.ca, pl.sr, pr.m, pr.k, pl.prow, nkb, 0, pr.logT, 0, 0};
+        const int32_t kshift = a_parent ? int32_t(pr.ca % 32) : 0;
+        // A panels are tasks [0, ncalls), B panels [ncalls, 2 ncalls); in the
+        // A-parent form the first A tasks pack the parents and the rest are empty
+        if (!a_parent)
+            hq.packs[q] =
+                PackTask{pr.A, Ap, pr.ra, pr.ca, pl.sr, pr.m, pr.k, pl.prow, nkb, 0, pr.logT, 0, 0};
+        else if (q < int64_t(apars.size()))
+            hq.packs[q] = PackTask{apars[q].A, (int8_t *)(ws + apars[q].off), 0, 0, 0,
+                                   apars[q].N, apars[q].N, apars[q].nslab * 32, apars[q].nkbp,
+                                   0, pr.logT, 0, 0};
+        else
+            hq.packs[q] = PackTask{nullptr, nullptr, 0, 0, 0, 0, 0, 0, 0, 0, pr.logT, 0, 0};
         hq.packs[ncalls + q] = PackTask{pr.B, Bp, pr.rb, pr.cb, pl.sc, pr.n, pr.k, pl.pcol, nkb,
-                                        1, pr.logT, pl.sub ? 1 : 0, 0};
+                                        1, pr.logT, pl.sub ? 1 : 0, kshift};
         LimbArgs &a = hq.calls[q];
         std::memset(&a, 0, sizeof(a));
         a.Ap = Ap;
@@ -317,6 +384,14 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
         a.bias = ((uint64_t(1) << 31) + p - 1) / p * p;
         a.pinv = 1.0 / double(p);
         a.logT = pr.logT;
+        if (a_parent) {
+            const AParent &ap = apars[apar_of[order[q]]];
+            const int64_t r0 = pr.ra - pl.sr;  // parent row of panel row 0 (may be < 0)
+            a.a_slab0 = r0 >= 0 ? r0 / 32 : -((31 - r0) / 32);
+            a.a_dr = int32_t(r0 - 32 * a.a_slab0);
+            a.a_kb0 = pr.ca / 32;
+            a.a_nkbp = ap.nkbp;
+        }
         hq.tile_prefix[q] = tile_total;
         tile_total += pl.grid_m * pl.grid_n;
     }
@@ -342,7 +417,8 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
         first_call += group_calls[g];
     }
 
-    hipGraphExec_t exec = ensure_graph(ctx, cfg, L, limb_batched_early_c(plans[0].pr.logT));
+    const bool early_c = limb_batched_early_c(plans[0].pr.logT);
+    hipGraphExec_t exec = ensure_graph(ctx, cfg, L, early_c, a_parent);
     if (!exec) return MH_E_DEVICE;
     hipError_t e = hipMemcpyAsync(b.queue_dev, b.queue_host, queue_bytes(b.queue_cap),
                                   hipMemcpyHostToDevice, stream);
@@ -355,6 +431,12 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
     if (e == hipSuccess && !c_override) {
         b.last_cfg = cfg;
         b.last_L = L;
+        // (the early-C form exists only for configurations with one 32 x 32
+        // block per wave and LDS stages, at L <= 2)
+        const LimbKernelCfg &kc = limb_cfg(cfg);
+        const bool has_early = kc.lds && kc.wm * kc.wn == 1 && L <= 2;
+        b.last_forms = (early_c && has_early ? MH_BATCH_FORM_EARLY_C : 0) |
+                       (a_parent ? MH_BATCH_FORM_A_PARENT : 0);
     }
     return note_error(ctx, e);
 }
@@ -363,11 +445,13 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
 
 using namespace mh;
 
-extern "C" mh_status mh_ctx_last_batch_config(mh_ctx *ctx, int32_t *cfg, int32_t *limbs)
+extern "C" mh_status mh_ctx_last_batch_config(mh_ctx *ctx, int32_t *cfg, int32_t *limbs,
+                                               int32_t *forms)
 {
     if (!ctx) return MH_E_INVALID;
     if (cfg) *cfg = ctx->batched.last_cfg;
     if (limbs) *limbs = ctx->batched.last_L;
+    if (forms) *forms = ctx->batched.last_forms;
     return MH_OK;
 }
 

@@ -36,8 +36,9 @@ struct BatchedState {
         hipGraphExec_t exec = nullptr;
     };
     std::map<int, Captured> graphs;
-    int last_cfg = -1;                  // configuration and limbs of the last batched graph
-    int last_L = 0;
+    int last_cfg = -1;                  // configuration, limbs and GEMM forms of the
+    int last_L = 0;                     //   last batched graph
+    int last_forms = 0;
 };
 
 struct DeviceGuard {

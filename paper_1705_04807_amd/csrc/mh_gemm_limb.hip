@@ -42,7 +42,7 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 // PIPE (LDS path): fragment reads one k-block ahead of the MFMAs, with a
 // second fragment set.
 template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF, bool PIPE,
-          bool EARLYC = false>
+          bool EARLYC = false, bool APAR = false>
 __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t gn)
 {
     constexpr int S = 2 * L - 1;
@@ -319,8 +319,13 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
         // the bare barrier below, about 6 % faster at L = 2).
         extern __shared__ v4i lds_buf[];  // [NBUF][NBLK][64]
         constexpr int NW = WAVES_M * WAVES_N;
-        constexpr int NA = WM * WAVES_M * KS * L;
-        constexpr int NBLK = (WM * WAVES_M + WN * WAVES_N) * KS * L;
+        // A from a whole-parent panel (APAR): the workgroup's rows start at
+        // row a_dr of a parent slab, so a stage holds one A slab more, and
+        // each lane reads its row from the slab (and row) it falls in.
+        constexpr bool kApar = APAR && WM == 1;
+        constexpr int SA = WM * WAVES_M + (kApar ? 1 : 0);  // A slabs per stage
+        constexpr int NA = SA * KS * L;
+        constexpr int NBLK = (SA + WN * WAVES_N) * KS * L;
         constexpr int R = (NBLK + NW - 1) / NW;  // 16-byte loads per wave and stage (at most)
         // With more than two buffers, the wait below lets this wave's loads of
         // the later stages stay outstanding; waves issue R or R - 1 loads per
@@ -348,11 +353,25 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
                     __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                         (void *)((isb ? gb : ga) + ((slab * nkb * L) << 10)), 0, slab_bytes,
                         0x00020000);
+                    int off = int(((kb + q) * L + t) << 10);
+                    if constexpr (kApar) {
+                        if (!isb) {
+                            // the parent's slab (the panel has guard slabs before
+                            // and after the parent's rows: rows outside the parent
+                            // only feed discarded outputs, and depths past the
+                            // product, read from the next slab, meet zero rows of B)
+                            const int64_t ps = a.a_slab0 + gm * WAVES_M + sl;
+                            rs = __builtin_amdgcn_make_buffer_rsrc(
+                                (void *)(ga + ps * ((a.a_nkbp * L) << 10)), 0, 0x7FFFFFFF,
+                                0x00020000);
+                            off = int(((a.a_kb0 + kb + q) * L + t) << 10);
+                        }
+                    }
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(
                         rs,
                         (__attribute__((address_space(3))) void *)(lds_buf +
                                                                     (buf * NBLK + b) * 64),
-                        16, int(lane_off), int(((kb + q) * L + t) << 10), 0, 0);
+                        16, int(lane_off), off, 0, 0);
                 }
             });
         };
@@ -389,11 +408,17 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
         // Fragments of k-block q of stage s, from LDS.
         using FragA1 = v4i[WM][L];
         using FragB1 = v4i[WN][L];
+        // (APAR) the lane's A row: slab ia / 32 of the stage, row ia % 32
+        const int ia = (kApar ? a.a_dr : 0) + wmi * 32 + (lane & 31);
+        const int a_slot = kApar ? ((ia >> 5) * KS * L) * 64 + (lane >> 5) * 32 + (ia & 31) : 0;
         auto read = [&](FragA1 &fa, FragB1 &fb, int64_t s, int q) {
             const v4i *sb = lds_buf + (s % NBUF) * (NBLK * 64) + lane;
             static_for<WM>([&](auto i) {
                 static_for<L>([&](auto t) {
-                    fa[i][t] = sb[(((wmi * WM + i) * KS + q) * L + t) * 64];
+                    if constexpr (kApar)
+                        fa[i][t] = lds_buf[(s % NBUF) * (NBLK * 64) + a_slot + (q * L + t) * 64];
+                    else
+                        fa[i][t] = sb[(((wmi * WM + i) * KS + q) * L + t) * 64];
                 });
             });
             static_for<WN>([&](auto j) {
@@ -509,7 +534,8 @@ k_gemm_limb(LimbArgs a)
 // the next block is issued when a block starts and read when it ends, so
 // its latency hides behind the block.  A forward search over the per-call
 // prefix sums finds the call of a block.
-template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF, bool EARLYC>
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF, bool EARLYC,
+          bool APAR>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N,
                              (WAVES_M * WAVES_N == 8 && WM * WN == 1 && L <= 2) ? 4 : 1) void
 k_gemm_limb_batched(
@@ -554,17 +580,19 @@ k_gemm_limb_batched(
             // that two workgroups share a compute unit and one's epilogue
             // and first loads overlap the other's MFMAs.
             constexpr bool kPipe = WAVES_M * WAVES_N <= 8 && WM * WN == 1 && L > 2;
-            gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, kPipe, EARLYC>(
+            gemm_tile<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, kPipe, EARLYC, APAR>(
                 a, local / a.grid_n, local % a.grid_n);
             cur = publish(next);
         }
     }
 }
 
-template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF>
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF,
+          bool APAR = false>
 constexpr size_t lds_bytes()
 {
-    return LDS ? size_t(NBUF) * (WM * WAVES_M + WN * WAVES_N) * KS * L * 1024 : 0;
+    return LDS ? size_t(NBUF) * (WM * WAVES_M + (APAR ? 1 : 0) + WN * WAVES_N) * KS * L * 1024
+               : 0;
 }
 
 template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF = 2>
@@ -616,26 +644,36 @@ bool cfg_fits(int L, const LimbKernelCfg &c)
     return (2 * L - 1) * c.wm * c.wn <= 14 && L <= c.lmax;
 }
 
-template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF = 2>
-hipError_t launch_batched_one(bool early_c, const QueueView &q, uint64_t *counters, int num_cu,
-                              hipStream_t s)
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF = 2,
+          bool CAN_APAR = false>
+hipError_t launch_batched_one(bool early_c, bool a_parent, const QueueView &q, uint64_t *counters,
+                              int num_cu, hipStream_t s)
 {
     // The early-C form exists where the kernel multiplies without a second
-    // fragment set, one 32 x 32 block per wave.
+    // fragment set, one 32 x 32 block per wave; the A-parent form for the
+    // configurations that name it.
     constexpr bool kCan = LDS && WM * WN == 1 && L <= 2;
-    auto kern = k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, false>;
+    constexpr bool kCanA = kCan && CAN_APAR;
+    using Kern = void (*)(const BatchHeader *, const LimbArgs *, const int64_t *, uint64_t *);
+    Kern kern = k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, false, false>;
+    size_t shm = lds_bytes<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>();
     if constexpr (kCan) {
-        if (early_c) kern = k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, true>;
+        if (early_c) kern = k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, true, false>;
     }
-    const size_t shm = lds_bytes<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>();
-    if (shm > 65536) {
-        static bool set[2] = {false, false};
-        if (!set[early_c && kCan] &&
-            hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                int(shm)) != hipSuccess)
-            return hipErrorInvalidValue;
-        set[early_c && kCan] = true;
+    if constexpr (kCanA) {
+        if (a_parent) {
+            kern = early_c
+                       ? k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, true, true>
+                       : k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, false, true>;
+            shm = lds_bytes<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, true>();
+        }
     }
+    if (a_parent && !kCanA) return hipErrorInvalidValue;
+    // (called while a graph is captured, once per graph)
+    if (shm > 65536 && hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           int(shm)) != hipSuccess)
+        return hipErrorInvalidValue;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * WAVES_M * WAVES_N, shm) !=
             hipSuccess || per_cu < 1)
@@ -646,38 +684,44 @@ hipError_t launch_batched_one(bool early_c, const QueueView &q, uint64_t *counte
 }
 
 template <int L>
-hipError_t dispatch_batched_L(int cfg, bool early_c, const QueueView &q, uint64_t *counters,
-                              int num_cu, hipStream_t s)
+hipError_t dispatch_batched_L(int cfg, bool early_c, bool a_parent, const QueueView &q,
+                              uint64_t *counters, int num_cu, hipStream_t s)
 {
     switch (cfg) {
-    case 0: return launch_batched_one<L, 1, 2, 2, 2, 1, false>(early_c, q, counters, num_cu, s);
-    case 1: return launch_batched_one<L, 1, 1, 2, 2, 1, false>(early_c, q, counters, num_cu, s);
-    case 2: return launch_batched_one<L, 2, 1, 2, 2, 1, false>(early_c, q, counters, num_cu, s);
+    case 0: return launch_batched_one<L, 1, 2, 2, 2, 1, false>(early_c, a_parent, q, counters, num_cu, s);
+    case 1: return launch_batched_one<L, 1, 1, 2, 2, 1, false>(early_c, a_parent, q, counters, num_cu, s);
+    case 2: return launch_batched_one<L, 2, 1, 2, 2, 1, false>(early_c, a_parent, q, counters, num_cu, s);
     case 3:
-        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 1, false>(early_c, q, counters, num_cu, s);
+        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 1, false>(early_c, a_parent, q, counters, num_cu, s);
         return hipErrorInvalidValue;
-    case 4: return launch_batched_one<L, 1, 2, 2, 2, 2, false>(early_c, q, counters, num_cu, s);
+    case 4: return launch_batched_one<L, 1, 2, 2, 2, 2, false>(early_c, a_parent, q, counters, num_cu, s);
     case 5:
-        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 2, false>(early_c, q, counters, num_cu, s);
+        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 2, false>(early_c, a_parent, q, counters, num_cu, s);
         return hipErrorInvalidValue;
-    case 6: return launch_batched_one<L, 1, 1, 2, 2, 2, false>(early_c, q, counters, num_cu, s);
-    case 7: return launch_batched_one<L, 1, 2, 2, 2, 2, true>(early_c, q, counters, num_cu, s);
+    case 6: return launch_batched_one<L, 1, 1, 2, 2, 2, false>(early_c, a_parent, q, counters, num_cu, s);
+    case 7: return launch_batched_one<L, 1, 2, 2, 2, 2, true>(early_c, a_parent, q, counters, num_cu, s);
     case 8:
-        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 2, true>(early_c, q, counters, num_cu, s);
+        if constexpr (L <= 2) return launch_batched_one<L, 2, 2, 2, 2, 2, true>(early_c, a_parent, q, counters, num_cu, s);
         return hipErrorInvalidValue;
-    case 9: return launch_batched_one<L, 1, 1, 2, 2, 2, true>(early_c, q, counters, num_cu, s);
-    case 10: return launch_batched_one<L, 2, 1, 2, 2, 2, true>(early_c, q, counters, num_cu, s);
-    case 11: return launch_batched_one<L, 1, 1, 2, 4, 2, true>(early_c, q, counters, num_cu, s);
-    case 12: return launch_batched_one<L, 1, 1, 4, 2, 2, true>(early_c, q, counters, num_cu, s);
+    case 9: return launch_batched_one<L, 1, 1, 2, 2, 2, true>(early_c, a_parent, q, counters, num_cu, s);
+    case 10: return launch_batched_one<L, 2, 1, 2, 2, 2, true>(early_c, a_parent, q, counters, num_cu, s);
+    case 11:
+        return launch_batched_one<L, 1, 1, 2, 4, 2, true, 2, true>(early_c, a_parent, q, counters,
+                                                                  num_cu, s);
+    case 12:
+        return launch_batched_one<L, 1, 1, 4, 2, 2, true, 2, true>(early_c, a_parent, q, counters,
+                                                                  num_cu, s);
     case 13:
-        if constexpr (L <= 2) return launch_batched_one<L, 1, 1, 4, 4, 2, true>(early_c, q, counters, num_cu, s);
+        if constexpr (L <= 2)
+            return launch_batched_one<L, 1, 1, 4, 4, 2, true, 2, true>(early_c, a_parent, q,
+                                                                      counters, num_cu, s);
         return hipErrorInvalidValue;
     case 14:
         if constexpr (L <= 2)
-            return launch_batched_one<L, 1, 1, 4, 4, 2, true, 3>(early_c, q, counters, num_cu, s);
+            return launch_batched_one<L, 1, 1, 4, 4, 2, true, 3>(early_c, a_parent, q, counters, num_cu, s);
         return hipErrorInvalidValue;
     case 15:
-        if constexpr (L <= 2) return launch_batched_one<L, 1, 2, 4, 2, 2, true>(early_c, q, counters, num_cu, s);
+        if constexpr (L <= 2) return launch_batched_one<L, 1, 2, 4, 2, 2, true>(early_c, a_parent, q, counters, num_cu, s);
         return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
@@ -739,16 +783,19 @@ int limb_cfg_default(int L, int64_t m, int64_t n, int64_t k)
 }
 
 bool limb_batched_early_c(int logT) { return logT >= 5 && logT <= 14; }
+bool limb_batched_a_parent(int cfg, int L) { return L <= 2 && cfg >= 11 && cfg <= 13; }
 
-hipError_t launch_gemm_limb_batched(int cfg, int L, bool early_c, const QueueView &q,
-                                    uint64_t *counters, int num_cu, hipStream_t s)
+hipError_t launch_gemm_limb_batched(int cfg, int L, bool early_c, bool a_parent,
+                                    const QueueView &q, uint64_t *counters, int num_cu,
+                                    hipStream_t s)
 {
     if (cfg < 0 || cfg >= limb_cfg_count() || !cfg_fits(L, kCfgs[cfg])) return hipErrorInvalidValue;
+    if (a_parent && !limb_batched_a_parent(cfg, L)) return hipErrorInvalidValue;
     switch (L) {
-    case 1: return dispatch_batched_L<1>(cfg, early_c, q, counters, num_cu, s);
-    case 2: return dispatch_batched_L<2>(cfg, early_c, q, counters, num_cu, s);
-    case 3: return dispatch_batched_L<3>(cfg, false, q, counters, num_cu, s);
-    case 4: return dispatch_batched_L<4>(cfg, false, q, counters, num_cu, s);
+    case 1: return dispatch_batched_L<1>(cfg, early_c, a_parent, q, counters, num_cu, s);
+    case 2: return dispatch_batched_L<2>(cfg, early_c, a_parent, q, counters, num_cu, s);
+    case 3: return dispatch_batched_L<3>(cfg, false, false, q, counters, num_cu, s);
+    case 4: return dispatch_batched_L<4>(cfg, false, false, q, counters, num_cu, s);
     }
     return hipErrorInvalidValue;
 }

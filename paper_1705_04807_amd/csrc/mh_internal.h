@@ -264,8 +264,19 @@ struct LimbArgs {
     uint64_t bias;       // multiple of p, >= 2^31
     double pinv;         // 1.0 / p rounded to nearest
     int logT;
+    // Batched form with A read from a whole-parent limb panel (Ap: its slab
+    // 0, with kAParentGuard slabs before and after the parent's): panel row 0
+    // of the product is parent row 32 a_slab0 + a_dr (0 <= a_dr < 32), its
+    // k-block 0 the parent's k-block a_kb0; a slab holds a_nkbp k-blocks.
+    int64_t a_slab0, a_kb0, a_nkbp;
+    int32_t a_dr, a_pad;
 };
 hipError_t launch_gemm_limb(int cfg, int L, const LimbArgs &a, hipStream_t s);
+// Guard slabs of a whole-parent A panel on each side: a product's panel rows
+// start at most min(T, 128) - 1 rows before the parent's and end at most 128
+// rows after, and its last k-block reaches at most two k-blocks into the
+// following slab.
+constexpr int64_t kAParentGuard = 6;
 
 // ------------------------------------------------------------ batch queue
 //
@@ -280,7 +291,8 @@ struct PackTask {
     int8_t *dst;
     int64_t r0, c0, shift, R, K, prow, nkb;
     int32_t trans, logT;
-    int32_t neg, pad;   // neg: pack (p - x) mod p
+    int32_t neg;        // pack (p - x) mod p
+    int32_t kshift;     // (trans only) depth kap holds source row r0 + kap - kshift
 };
 
 // Output blocks of a batch are split into kXcdGroups groups of whole
@@ -336,10 +348,14 @@ constexpr int kBatchCounters = 2 + kXcdGroups;
 hipError_t launch_pack_limb_batched(int L, const QueueView &q, uint64_t *counters, int num_cu,
                                     hipStream_t s);
 // early_c: the form that loads C ahead of the epilogue (valid when
-// limb_batched_early_c(logT) holds for the batch's tile size).
+// limb_batched_early_c(logT) holds for the batch's tile size); a_parent: the
+// form that reads A from whole-parent panels (configurations for which
+// limb_batched_a_parent(cfg, L) holds).
 bool limb_batched_early_c(int logT);
-hipError_t launch_gemm_limb_batched(int cfg, int L, bool early_c, const QueueView &q,
-                                    uint64_t *counters, int num_cu, hipStream_t s);
+bool limb_batched_a_parent(int cfg, int L);
+hipError_t launch_gemm_limb_batched(int cfg, int L, bool early_c, bool a_parent,
+                                    const QueueView &q, uint64_t *counters, int num_cu,
+                                    hipStream_t s);
 hipError_t launch_reset_counters(uint64_t *counters, hipStream_t s);
 
 }  // namespace mh

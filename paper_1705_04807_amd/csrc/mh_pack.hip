@@ -87,14 +87,15 @@ __device__ __forceinline__ void digits16(const uint32_t *x, uint32_t p, int32_t 
 // (slab, kb, limb); lane q of a block holds row (q & 31), depth
 // (q >> 5) * 16 .. +15.  One workgroup packs 64 panel rows x 64 depth
 // (2 slabs x 2 k-blocks).  trans = 0: panel (rho, kap) <- src(r0 + rho -
-// shift, c0 + kap); trans = 1: src(r0 + kap, c0 + rho - shift).  Entries
-// with rho outside [shift, shift + R) or kap >= K are zero.
+// shift, c0 + kap); trans = 1: src(r0 + kap - kshift, c0 + rho - shift).
+// Entries with rho outside [shift, shift + R) or kap outside [kshift,
+// kshift + K) are zero (kshift = 0 when trans = 0).
 template <int L, bool TRANS>
 __device__ __forceinline__ void pack_chunk(int8_t *__restrict__ dst, int64_t nkb,
                                            const uint32_t *__restrict__ src, int64_t r0,
                                            int64_t c0, int64_t shift, int64_t R, int64_t K,
                                            int logT, uint32_t p, int32_t H, int64_t rho0,
-                                           int64_t kap0, uint32_t *tile, int neg)
+                                           int64_t kap0, uint32_t *tile, int neg, int64_t kshift)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
@@ -130,8 +131,8 @@ __device__ __forceinline__ void pack_chunk(int8_t *__restrict__ dst, int64_t nkb
                 srow = r0 + rho - shift;
             } else {
                 const int64_t kap = kap0 + other;
-                ok = kap < K;
-                srow = r0 + kap;
+                ok = kap >= kshift && kap < kshift + K;
+                srow = r0 + kap - kshift;
             }
             // the 17th group is needed only when the window starts inside a group
             ok = ok && gcol + 4 > clo && gcol < chi && (mis != 0 || g < G - 1);
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(256) void k_pack_limb(int8_t *__restrict__ dst, int
 {
     __shared__ uint32_t tile[kChunk * kLdsStride];
     pack_chunk<L, TRANS>(dst, nkb, src, r0, c0, shift, R, K, logT, p, H,
-                         int64_t(blockIdx.y) * kChunk, int64_t(blockIdx.x) * kChunk, tile, neg);
+                         int64_t(blockIdx.y) * kChunk, int64_t(blockIdx.x) * kChunk, tile, neg, 0);
 }
 
 // Persistent form for a batch: workgroups pop runs of 64 x 64 chunks of all
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(256) void k_pack_limb_batched(const BatchHeader *__
             const int64_t rho0 = (local / kchunks) * kChunk, kap0 = (local % kchunks) * kChunk;
             if (c > c0) __syncthreads();  // the previous chunk's LDS reads are done
             pack_chunk<L, TRANS>(t.dst, t.nkb, t.src, t.r0, t.c0, t.shift, t.R, t.K, t.logT, p, H,
-                                 rho0, kap0, tile, t.neg);
+                                 rho0, kap0, tile, t.neg, TRANS ? int64_t(t.kshift) : 0);
         }
     }
 }

@@ -77,12 +77,17 @@ def test_batched_random(mh, ctx, mode, p, T):
     run_batch(mh, ctx, calls, A, B, Cs, Ad, Bd, Cds, NA, NB, NC, p, T, mode)
 
 
-@pytest.mark.parametrize("p,T", [(65521, 32), (65521, 128), (251, 64), (251, 32)])
-def test_batched_early_c_forms(mh, ctx, p, T):
-    """The persistent GEMM form that loads C two stages ahead of the epilogue
-    (one and two limbs, 32 <= T): tile sizes other than 64, and thin products
-    whose output blocks leave whole waves of a workgroup outside them (those
-    waves load words they discard and store nothing)."""
+@pytest.mark.parametrize("apar", ["0", "1"])
+@pytest.mark.parametrize("p,T", [(65521, 32), (65521, 128), (251, 64), (251, 32), (65521, 16)])
+def test_batched_early_c_forms(mh, ctx, monkeypatch, apar, p, T):
+    """The persistent GEMM forms that load C two stages ahead of the epilogue
+    (one and two limbs, 32 <= T) and that read A from a panel of the whole
+    parent (MH_BATCH_APARENT=1; A blocks at every row and column phase,
+    including blocks at the parent's edges and panels starting above the
+    parent's first row): tile sizes other than 64, and thin products whose
+    output blocks leave whole waves of a workgroup outside them (those waves
+    load words they discard and store nothing)."""
+    monkeypatch.setenv("MH_BATCH_APARENT", apar)
     g = np.random.default_rng(950 + T + p % 97)
     NA = NB = NC = 1024
     nC = 3
@@ -95,6 +100,13 @@ def test_batched_early_c_forms(mh, ctx, p, T):
         m, k, n = 1 + 7 * i, 33 + 50 * i, 100 + 37 * i
         calls.append(dict(ci=2, rc=5 + 150 * i, cc=17 + 3 * i, m=m, k=k, n=n,
                           ra=int(g.integers(0, NA - m + 1)), ca=int(g.integers(0, NA - k + 1)),
+                          rb=int(g.integers(0, NB - k + 1)), cb=int(g.integers(0, NB - n + 1))))
+    # A blocks at the parent's corners (first row and column, last row and
+    # column) with C offsets whose row phase exceeds A's first row
+    for i, (ra, ca, m, k) in enumerate([(0, 0, 70, 90), (NA - 45, NA - 77, 45, 77),
+                                        (3, NA - 200, 90, 200), (NA - 90, 1, 90, 31)]):
+        n = 50 + 20 * i
+        calls.append(dict(ci=2, rc=930 + i % 2, cc=400 + 150 * i, m=m, k=k, n=n, ra=ra, ca=ca,
                           rb=int(g.integers(0, NB - k + 1)), cb=int(g.integers(0, NB - n + 1))))
     say("batched early C", p, T, len(calls))
     run_batch(mh, ctx, calls, A, B, Cs, Ad, Bd, Cds, NA, NB, NC, p, T, 2)

@@ -98,3 +98,31 @@ def test_batched_configuration(mh, ctx, batches, monkeypatch, L, cfg, kblock):
     for ci, Cd in enumerate(Cds):
         assert np.array_equal(host_of(to_cart(mh, ctx, Cd, N, T)), want[ci]), ci
     assert mh.mh_ctx_last_device_error(ctx) == 0
+
+
+@pytest.mark.parametrize("kblock", [None, 128])
+@pytest.mark.parametrize("cfg", [11, 12, 13])
+def test_batched_configuration_a_parent(mh, ctx, batches, monkeypatch, cfg, kblock):
+    """The configurations with the form that reads A from a panel of the
+    whole parent (forced with MH_BATCH_APARENT=1), at two limbs."""
+    L, p = 2, PRIMES[2]
+    monkeypatch.setenv("MH_LIMB_CFG", str(cfg))
+    monkeypatch.setenv("MH_BATCH_APARENT", "1")
+    if kblock:
+        monkeypatch.setenv("MH_LIMB_KBLOCK", str(kblock))
+    else:
+        monkeypatch.delenv("MH_LIMB_KBLOCK", raising=False)
+    calls, Cs, want, Ad, Bd = batches[L]
+    Cds = [to_mh(mh, ctx, device_of(C), N, T) for C in Cs]
+    descs = mh.make_descs([dict(C=Cds[c["ci"]].data_ptr(), A=Ad.data_ptr(), B=Bd.data_ptr(),
+                                NC=N, NA=N, NB=N, rc=c["rc"], cc=c["cc"], ra=c["ra"],
+                                ca=c["ca"], rb=c["rb"], cb=c["cb"], m=c["m"], k=c["k"],
+                                n=c["n"]) for c in calls])
+    say("batched a-parent cfg", cfg, "kblock", kblock)
+    mh.check(mh.mh_matmul_modp_batched(ctx, descs, len(calls), p, T, mh.MH_MODE_LIMB_I8,
+                                       stream_handle()), "batched")
+    s, last_cfg, _, forms = mh.mh_ctx_last_batch_config(ctx)
+    assert last_cfg == cfg and forms & mh.MH_BATCH_FORM_A_PARENT
+    for ci, Cd in enumerate(Cds):
+        assert np.array_equal(host_of(to_cart(mh, ctx, Cd, N, T)), want[ci]), ci
+    assert mh.mh_ctx_last_device_error(ctx) == 0
