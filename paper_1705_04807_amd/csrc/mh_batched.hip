@@ -237,10 +237,73 @@ namespace mh {
 // Runs products already planned with kernel configuration cfg as one
 // batched graph on `stream`.  With c_override set, every output goes to that
 // buffer instead (tuning runs).
-mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int L, uint32_t p,
+mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans0, int cfg, int L, uint32_t p,
                        hipStream_t stream, uint32_t *c_override)
 {
-    if (plans.empty()) return MH_OK;
+    if (plans0.empty()) return MH_OK;
+    // C loaded ahead of the epilogue: tile size and C parents permitting.
+    int64_t max_nc = 0;
+    for (const Plan &pl : plans0) max_nc = std::max<int64_t>(max_nc, pl.pr.NC);
+    const bool early_c = limb_batched_early_c(plans0[0].pr.logT, max_nc);
+
+    // A operands from whole-parent panels: each distinct A parent is packed
+    // once, and the GEMM reads every product's A block out of its parent's
+    // panel (a TU level's products are blocks of a few shared parents, each
+    // word of which lies in many products' A blocks).  Chosen when the A
+    // blocks hold at least as many words as their parents (MH_BATCH_APARENT
+    // = 0 never, 1 whenever the configuration has that form), with the
+    // early-C form, and every parent panel below 2 GiB.  Each product's panel
+    // rows then start on a 32-row slab of its A parent (row shift ra mod 32
+    // instead of C's tile phase: the early-C epilogue addresses C rows of
+    // any phase), and B's panels start their depth at the phase ca mod 32 of
+    // A's columns in the parent's k-blocks.
+    struct AParent {
+        const uint32_t *A;
+        int64_t N, nslab, nkbp;
+        size_t off;
+    };
+    std::vector<AParent> apars;
+    std::vector<int> apar_of(plans0.size(), -1);
+    bool a_parent = early_c && limb_batched_a_parent(cfg, L);
+    if (a_parent) {
+        const char *env = std::getenv("MH_BATCH_APARENT");
+        const int want = env ? std::atoi(env) : -1;
+        double words = 0.0, pwords = 0.0;
+        for (size_t q = 0; q < plans0.size() && a_parent; ++q) {
+            const Product &pr = plans0[q].pr;
+            words += double(pr.m) * double(pr.k);
+            int idx = -1;
+            for (size_t u = 0; u < apars.size(); ++u)
+                if (apars[u].A == pr.A && apars[u].N == pr.NA) idx = int(u);
+            if (idx < 0) {
+                AParent ap;
+                ap.A = pr.A;
+                ap.N = pr.NA;
+                ap.nslab = (pr.NA + 63) / 64 * 2;  // rows in whole 64-row pack chunks
+                ap.nkbp = (pr.NA + 63) / 64 * 2;   // an even number of k-blocks
+                ap.off = 0;
+                if ((ap.nslab + kAParentGuard) * ap.nkbp * L * 1024 >= (int64_t(1) << 31))
+                    a_parent = false;
+                pwords += double(pr.NA) * double(pr.NA);
+                apars.push_back(ap);
+                idx = int(apars.size()) - 1;
+            }
+            apar_of[q] = idx;
+        }
+        a_parent = a_parent && want != 0 && (want == 1 || words >= pwords);
+    }
+    std::vector<Plan> shifted;
+    if (a_parent) {
+        shifted = plans0;
+        for (Plan &pl : shifted) {
+            pl.sr = pl.pr.ra % 32;
+            pl.row0C = pl.pr.rc - pl.sr;
+            pl.prow = (pl.sr + pl.pr.m + pl.tile_m - 1) / pl.tile_m * pl.tile_m;
+            pl.grid_m = pl.prow / pl.tile_m;
+        }
+    }
+    const std::vector<Plan> &plans = a_parent ? shifted : plans0;
+
     // Longest-processing-time order: every output block of a product costs
     // its k, so products with the longest k go first.  In that order each
     // product joins the XCD group with the least work so far (blocks x k);
@@ -265,49 +328,6 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
     std::stable_sort(order.begin(), order.end(),
                      [&](size_t a, size_t b) { return grp[a] < grp[b]; });
 
-    // A operands from whole-parent panels: each distinct A parent is packed
-    // once, and the GEMM reads every product's A block out of its parent's
-    // panel (a TU level's products are blocks of a few shared parents, each
-    // word of which lies in many products' A blocks).  Chosen when the A
-    // blocks hold at least as many words as their parents (MH_BATCH_APARENT
-    // = 0 never, 1 whenever the configuration has that form), and every
-    // parent panel stays below 2 GiB.  B's panels then start their depth at
-    // the phase ca mod 32 of A's columns in the parent's k-blocks.
-    struct AParent {
-        const uint32_t *A;
-        int64_t N, nslab, nkbp;
-        size_t off;
-    };
-    std::vector<AParent> apars;
-    std::vector<int> apar_of(plans.size(), -1);
-    bool a_parent = limb_batched_a_parent(cfg, L);
-    if (a_parent) {
-        const char *env = std::getenv("MH_BATCH_APARENT");
-        const int want = env ? std::atoi(env) : -1;
-        double words = 0.0, pwords = 0.0;
-        for (size_t q = 0; q < plans.size() && a_parent; ++q) {
-            const Product &pr = plans[q].pr;
-            words += double(pr.m) * double(pr.k);
-            int idx = -1;
-            for (size_t u = 0; u < apars.size(); ++u)
-                if (apars[u].A == pr.A && apars[u].N == pr.NA) idx = int(u);
-            if (idx < 0) {
-                AParent ap;
-                ap.A = pr.A;
-                ap.N = pr.NA;
-                ap.nslab = (pr.NA + 63) / 64 * 2;  // rows in whole 64-row pack chunks
-                ap.nkbp = (pr.NA + 63) / 64 * 2;   // an even number of k-blocks
-                ap.off = 0;
-                if ((ap.nslab + 2 * kAParentGuard) * ap.nkbp * L * 1024 >= (int64_t(1) << 31))
-                    a_parent = false;
-                pwords += double(pr.NA) * double(pr.NA);
-                apars.push_back(ap);
-                idx = int(apars.size()) - 1;
-            }
-            apar_of[q] = idx;
-        }
-        a_parent = a_parent && want != 0 && (want == 1 || words >= pwords);
-    }
     // GEMM k-blocks of each product (A-parent form: from the phase of ca)
     std::vector<int64_t> nkbs(plans.size());
     for (size_t q = 0; q < plans.size(); ++q) {
@@ -322,8 +342,8 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
     if (a_parent)
         for (AParent &ap : apars) {
             const size_t slab = size_t(ap.nkbp) * size_t(L) * 1024;
-            ap.off = total + size_t(kAParentGuard) * slab;
-            total += align256((size_t(ap.nslab) + 2 * size_t(kAParentGuard)) * slab);
+            ap.off = total;
+            total += align256((size_t(ap.nslab) + size_t(kAParentGuard)) * slab);
         }
     for (size_t q = 0; q < plans.size(); ++q) {
         const Plan &pl = plans[q];
@@ -386,9 +406,7 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
         a.logT = pr.logT;
         if (a_parent) {
             const AParent &ap = apars[apar_of[order[q]]];
-            const int64_t r0 = pr.ra - pl.sr;  // parent row of panel row 0 (may be < 0)
-            a.a_slab0 = r0 >= 0 ? r0 / 32 : -((31 - r0) / 32);
-            a.a_dr = int32_t(r0 - 32 * a.a_slab0);
+            a.a_slab0 = (pr.ra - pl.sr) / 32;  // (ra - sr is a multiple of 32)
             a.a_kb0 = pr.ca / 32;
             a.a_nkbp = ap.nkbp;
         }
@@ -417,7 +435,6 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans, int cfg, int
         first_call += group_calls[g];
     }
 
-    const bool early_c = limb_batched_early_c(plans[0].pr.logT);
     hipGraphExec_t exec = ensure_graph(ctx, cfg, L, early_c, a_parent);
     if (!exec) return MH_E_DEVICE;
     hipError_t e = hipMemcpyAsync(b.queue_dev, b.queue_host, queue_bytes(b.queue_cap),

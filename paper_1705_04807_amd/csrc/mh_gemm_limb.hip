@@ -67,43 +67,50 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
     // C words of the wave's outputs loaded kCLead stages ahead of the
     // epilogue (one 32 x 32 block per wave, at L <= 2 in the persistent
     // kernel: a block there is a short pipeline, and its C round trip would
-    // otherwise stall the waves between two blocks).  The panel shifts start
-    // the wave's block on multiples of min(T, 32) in C's rows and columns,
-    // so for 32 <= T <= 2^14 (the launch selects this form only then) it
-    // lies inside one T x T tile: one base per wave and 32-bit byte offsets
-    // per output keep the 16 loads within a few registers.  A wave whose block lies wholly outside the output
-    // block reads C(rc, cc) instead, and out-of-block outputs read (and
-    // discard) words of their valid tile, so every wave issues all 16
-    // loads, without branches, and the stage waits can count them.
+    // otherwise stall the waves between two blocks).  The launch selects
+    // this form for T >= 32 and C parents of at most 2^30 words, so 32
+    // consecutive rows (columns) lie in at most two tile rows (columns), and
+    // every word has a 32-bit byte offset from the parent's base: per lane,
+    // the offsets of its column in the two tile rows, and per output a
+    // select, keep the 16 loads within a few registers.  Rows and columns
+    // are clamped into the output block (a wave wholly outside it takes the
+    // block's first rows and columns), so every wave issues all 16 loads,
+    // to valid words, without branches, and the stage waits can count them;
+    // out-of-block outputs discard theirs.
     constexpr bool kEarlyC = EARLYC && LDS && !PIPE && WM * WN == 1;
     uint32_t cpre[16];
     auto c_tile = [&](auto &&f) {
         // f(v, inside, base, byte offset) for the lane's 16 outputs
-        const uint32_t tmask = (1u << a.logT) - 1;
+        const int lt = a.logT;
+        const uint32_t tmask = (1u << lt) - 1;
         const int wu = __builtin_amdgcn_readfirstlane(wave);  // (wave-uniform: scalar)
         const int64_t rho0 = gm * BM + (wu / WAVES_N) * 32, gam0 = gn * BN + (wu % WAVES_N) * 32;
         const bool any = rho0 < a.sr + a.m && rho0 + 32 > a.sr && gam0 < a.sc + a.n &&
                          gam0 + 32 > a.sc;
-        // (a wave outside the block reads the 32-aligned 32 x 32 block
-        // around C(rc, cc), inside that word's tile)
-        const uint32_t R0 = any ? uint32_t(a.row0C + rho0) : uint32_t(a.row0C + a.sr) & ~31u;
-        const uint32_t C0 = any ? uint32_t(a.col0C + gam0) : uint32_t(a.col0C + a.sc) & ~31u;
-        const uint64_t tile = uint64_t((spread16(R0 >> a.logT) << 1) | spread16(C0 >> a.logT))
-                              << (2 * a.logT);
-        gu32 *const base = Cg + tile;
-        uint32_t off = ((((R0 & tmask) + uint32_t((lane >> 5) * 4)) << a.logT) + (C0 & tmask) +
-                        uint32_t(lane & 31))
-                       << 2;
+        const uint32_t rlo = uint32_t(a.row0C + a.sr), rhi = rlo + uint32_t(a.m) - 1;
+        const uint32_t clo = uint32_t(a.col0C + a.sc), chi = clo + uint32_t(a.n) - 1;
+        const uint32_t R0 = any ? uint32_t(a.row0C + rho0) : rlo;
+        const uint32_t C0 = any ? uint32_t(a.col0C + gam0) : clo;
+        const uint32_t tr0 = R0 >> lt, tc0 = C0 >> lt;
+        const uint32_t bR = (tr0 + 1) << lt, bC = (tc0 + 1) << lt;  // next tile row / column
+        uint32_t col = C0 + uint32_t(lane & 31);
+        const bool col_in = any && col >= clo && col <= chi;
+        col = col < clo ? clo : (col > chi ? chi : col);
+        const uint32_t tcl = col >= bC ? tc0 + 1 : tc0;
+        // word offsets of the lane's column in tile rows tr0 and tr0 + 1 (the
+        // second is used only by rows that lie there, so its tile exists)
+        uint32_t baseU = ((((spread16(tr0) << 1) | spread16(tcl)) << (2 * lt)) | (col & tmask));
+        uint32_t baseL = ((((spread16(tr0 + 1) << 1) | spread16(tcl)) << (2 * lt)) | (col & tmask));
         // (computed where used: hoisted out of the k loop, the addresses
         // would hold registers through it)
-        asm volatile("" : "+v"(off));
-        const int64_t gam = gam0 + (lane & 31);
-        const bool col_in = any && gam >= a.sc && gam < a.sc + a.n;
+        asm volatile("" : "+v"(baseU), "+v"(baseL));
+        const uint32_t rl = R0 + uint32_t((lane >> 5) * 4);
         static_for<16>([&](auto v) {
             constexpr int drow = (int(v) >> 2) * 8 + (int(v) & 3);
-            const int64_t rho = rho0 + drow + (lane >> 5) * 4;
-            const bool in = col_in && rho >= a.sr && rho < a.sr + a.m;
-            f(v, in, base, off + (uint32_t(drow) << (a.logT + 2)));
+            uint32_t row = rl + uint32_t(drow);
+            const bool in = col_in && row >= rlo && row <= rhi;
+            row = row < rlo ? rlo : (row > rhi ? rhi : row);
+            f(v, in, Cg, ((row >= bR ? baseL : baseU) + ((row & tmask) << lt)) << 2);
         });
     };
     auto word = [](gu32 *base, uint32_t byte_off) -> gu32 & {
@@ -319,13 +326,11 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
         // the bare barrier below, about 6 % faster at L = 2).
         extern __shared__ v4i lds_buf[];  // [NBUF][NBLK][64]
         constexpr int NW = WAVES_M * WAVES_N;
-        // A from a whole-parent panel (APAR): the workgroup's rows start at
-        // row a_dr of a parent slab, so a stage holds one A slab more, and
-        // each lane reads its row from the slab (and row) it falls in.
-        constexpr bool kApar = APAR && WM == 1;
-        constexpr int SA = WM * WAVES_M + (kApar ? 1 : 0);  // A slabs per stage
-        constexpr int NA = SA * KS * L;
-        constexpr int NBLK = (SA + WN * WAVES_N) * KS * L;
+        // A from a whole-parent panel (APAR): the launch starts the panel
+        // rows on a parent slab, so the A blocks of a stage are the parent's.
+        constexpr bool kApar = APAR;
+        constexpr int NA = WM * WAVES_M * KS * L;
+        constexpr int NBLK = (WM * WAVES_M + WN * WAVES_N) * KS * L;
         constexpr int R = (NBLK + NW - 1) / NW;  // 16-byte loads per wave and stage (at most)
         // With more than two buffers, the wait below lets this wave's loads of
         // the later stages stay outstanding; waves issue R or R - 1 loads per
@@ -356,10 +361,10 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
                     int off = int(((kb + q) * L + t) << 10);
                     if constexpr (kApar) {
                         if (!isb) {
-                            // the parent's slab (the panel has guard slabs before
-                            // and after the parent's rows: rows outside the parent
-                            // only feed discarded outputs, and depths past the
-                            // product, read from the next slab, meet zero rows of B)
+                            // the parent's slab (the panel has guard slabs after
+                            // the parent's rows: rows past the parent only feed
+                            // discarded outputs, and depths past the product, read
+                            // from the next slab, meet zero rows of B)
                             const int64_t ps = a.a_slab0 + gm * WAVES_M + sl;
                             rs = __builtin_amdgcn_make_buffer_rsrc(
                                 (void *)(ga + ps * ((a.a_nkbp * L) << 10)), 0, 0x7FFFFFFF,
@@ -408,17 +413,11 @@ __device__ __forceinline__ void gemm_tile(const LimbArgs &a, int64_t gm, int64_t
         // Fragments of k-block q of stage s, from LDS.
         using FragA1 = v4i[WM][L];
         using FragB1 = v4i[WN][L];
-        // (APAR) the lane's A row: slab ia / 32 of the stage, row ia % 32
-        const int ia = (kApar ? a.a_dr : 0) + wmi * 32 + (lane & 31);
-        const int a_slot = kApar ? ((ia >> 5) * KS * L) * 64 + (lane >> 5) * 32 + (ia & 31) : 0;
         auto read = [&](FragA1 &fa, FragB1 &fb, int64_t s, int q) {
             const v4i *sb = lds_buf + (s % NBUF) * (NBLK * 64) + lane;
             static_for<WM>([&](auto i) {
                 static_for<L>([&](auto t) {
-                    if constexpr (kApar)
-                        fa[i][t] = lds_buf[(s % NBUF) * (NBLK * 64) + a_slot + (q * L + t) * 64];
-                    else
-                        fa[i][t] = sb[(((wmi * WM + i) * KS + q) * L + t) * 64];
+                    fa[i][t] = sb[(((wmi * WM + i) * KS + q) * L + t) * 64];
                 });
             });
             static_for<WN>([&](auto j) {
@@ -587,12 +586,10 @@ k_gemm_limb_batched(
     }
 }
 
-template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF,
-          bool APAR = false>
+template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF>
 constexpr size_t lds_bytes()
 {
-    return LDS ? size_t(NBUF) * (WM * WAVES_M + (APAR ? 1 : 0) + WN * WAVES_N) * KS * L * 1024
-               : 0;
+    return LDS ? size_t(NBUF) * (WM * WAVES_M + WN * WAVES_N) * KS * L * 1024 : 0;
 }
 
 template <int L, int WM, int WN, int WAVES_M, int WAVES_N, int KS, bool LDS, int NBUF = 2>
@@ -656,7 +653,7 @@ hipError_t launch_batched_one(bool early_c, bool a_parent, const QueueView &q, u
     constexpr bool kCanA = kCan && CAN_APAR;
     using Kern = void (*)(const BatchHeader *, const LimbArgs *, const int64_t *, uint64_t *);
     Kern kern = k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, false, false>;
-    size_t shm = lds_bytes<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>();
+    const size_t shm = lds_bytes<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF>();
     if constexpr (kCan) {
         if (early_c) kern = k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, true, false>;
     }
@@ -665,7 +662,6 @@ hipError_t launch_batched_one(bool early_c, bool a_parent, const QueueView &q, u
             kern = early_c
                        ? k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, true, true>
                        : k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, false, true>;
-            shm = lds_bytes<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, true>();
         }
     }
     if (a_parent && !kCanA) return hipErrorInvalidValue;
@@ -782,7 +778,10 @@ int limb_cfg_default(int L, int64_t m, int64_t n, int64_t k)
     return L <= 2 ? 11 : 9;
 }
 
-bool limb_batched_early_c(int logT) { return logT >= 5 && logT <= 14; }
+bool limb_batched_early_c(int logT, int64_t max_nc)
+{
+    return logT >= 5 && max_nc <= (int64_t(1) << 15);
+}
 bool limb_batched_a_parent(int cfg, int L) { return L <= 2 && cfg >= 11 && cfg <= 13; }
 
 hipError_t launch_gemm_limb_batched(int cfg, int L, bool early_c, bool a_parent,

@@ -265,17 +265,15 @@ struct LimbArgs {
     double pinv;         // 1.0 / p rounded to nearest
     int logT;
     // Batched form with A read from a whole-parent limb panel (Ap: its slab
-    // 0, with kAParentGuard slabs before and after the parent's): panel row 0
-    // of the product is parent row 32 a_slab0 + a_dr (0 <= a_dr < 32), its
-    // k-block 0 the parent's k-block a_kb0; a slab holds a_nkbp k-blocks.
+    // 0, with kAParentGuard slabs after the parent's): panel row 0 of the
+    // product is the parent's row 32 a_slab0, its k-block 0 the parent's
+    // k-block a_kb0; a slab holds a_nkbp k-blocks.
     int64_t a_slab0, a_kb0, a_nkbp;
-    int32_t a_dr, a_pad;
 };
 hipError_t launch_gemm_limb(int cfg, int L, const LimbArgs &a, hipStream_t s);
-// Guard slabs of a whole-parent A panel on each side: a product's panel rows
-// start at most min(T, 128) - 1 rows before the parent's and end at most 128
-// rows after, and its last k-block reaches at most two k-blocks into the
-// following slab.
+// Guard slabs after a whole-parent A panel: a product's panel rows end at
+// most 128 rows after the parent's, and its last k-block reaches at most one
+// k-block into the following slab.
 constexpr int64_t kAParentGuard = 6;
 
 // ------------------------------------------------------------ batch queue
@@ -348,10 +346,11 @@ constexpr int kBatchCounters = 2 + kXcdGroups;
 hipError_t launch_pack_limb_batched(int L, const QueueView &q, uint64_t *counters, int num_cu,
                                     hipStream_t s);
 // early_c: the form that loads C ahead of the epilogue (valid when
-// limb_batched_early_c(logT) holds for the batch's tile size); a_parent: the
-// form that reads A from whole-parent panels (configurations for which
-// limb_batched_a_parent(cfg, L) holds).
-bool limb_batched_early_c(int logT);
+// limb_batched_early_c(logT, largest C parent) holds); a_parent: the form
+// that reads A from whole-parent panels (configurations for which
+// limb_batched_a_parent(cfg, L) holds, with early_c, and panel rows that
+// start on a 32-row slab of the A parent).
+bool limb_batched_early_c(int logT, int64_t max_nc);
 bool limb_batched_a_parent(int cfg, int L);
 hipError_t launch_gemm_limb_batched(int cfg, int L, bool early_c, bool a_parent,
                                     const QueueView &q, uint64_t *counters, int num_cu,
