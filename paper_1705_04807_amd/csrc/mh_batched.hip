@@ -241,10 +241,14 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans0, int cfg, in
                        hipStream_t stream, uint32_t *c_override)
 {
     if (plans0.empty()) return MH_OK;
-    // C loaded ahead of the epilogue: tile size and C parents permitting.
+    // C loaded ahead of the epilogue: where the configuration has that form
+    // (one 32 x 32 block per wave, LDS stages, L <= 2), tile size and C
+    // parents permitting.
     int64_t max_nc = 0;
     for (const Plan &pl : plans0) max_nc = std::max<int64_t>(max_nc, pl.pr.NC);
-    const bool early_c = limb_batched_early_c(plans0[0].pr.logT, max_nc);
+    const LimbKernelCfg &kc = limb_cfg(cfg);
+    const bool early_c = kc.lds && kc.wm * kc.wn == 1 && L <= 2 &&
+                         limb_batched_early_c(plans0[0].pr.logT, max_nc);
 
     // A operands from whole-parent panels: each distinct A parent is packed
     // once, and the GEMM reads every product's A block out of its parent's
@@ -292,17 +296,22 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans0, int cfg, in
         }
         a_parent = a_parent && want != 0 && (want == 1 || words >= pwords);
     }
+    // The early-C epilogue addresses C rows at any phase, so the row shift
+    // need not align the output blocks with C's tile rows: none (fewer
+    // padded rows), or A's slab phase.  The column shift stays: with C's
+    // columns on its tile grid, each row of a wave's 32 outputs is one
+    // 128-byte line.
     std::vector<Plan> shifted;
-    if (a_parent) {
+    if (early_c) {
         shifted = plans0;
         for (Plan &pl : shifted) {
-            pl.sr = pl.pr.ra % 32;
+            pl.sr = a_parent ? pl.pr.ra % 32 : 0;
             pl.row0C = pl.pr.rc - pl.sr;
             pl.prow = (pl.sr + pl.pr.m + pl.tile_m - 1) / pl.tile_m * pl.tile_m;
             pl.grid_m = pl.prow / pl.tile_m;
         }
     }
-    const std::vector<Plan> &plans = a_parent ? shifted : plans0;
+    const std::vector<Plan> &plans = early_c ? shifted : plans0;
 
     // Longest-processing-time order: every output block of a product costs
     // its k, so products with the longest k go first.  In that order each
@@ -448,11 +457,7 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans0, int cfg, in
     if (e == hipSuccess && !c_override) {
         b.last_cfg = cfg;
         b.last_L = L;
-        // (the early-C form exists only for configurations with one 32 x 32
-        // block per wave and LDS stages, at L <= 2)
-        const LimbKernelCfg &kc = limb_cfg(cfg);
-        const bool has_early = kc.lds && kc.wm * kc.wn == 1 && L <= 2;
-        b.last_forms = (early_c && has_early ? MH_BATCH_FORM_EARLY_C : 0) |
+        b.last_forms = (early_c ? MH_BATCH_FORM_EARLY_C : 0) |
                        (a_parent ? MH_BATCH_FORM_A_PARENT : 0);
     }
     return note_error(ctx, e);

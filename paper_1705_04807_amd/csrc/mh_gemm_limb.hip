@@ -664,7 +664,9 @@ hipError_t launch_batched_one(bool early_c, bool a_parent, const QueueView &q, u
                        : k_gemm_limb_batched<L, WM, WN, WAVES_M, WAVES_N, KS, LDS, NBUF, false, true>;
         }
     }
-    if (a_parent && !kCanA) return hipErrorInvalidValue;
+    // (the host drops the panel shifts for the early-C form: a kernel without
+    // it would misplace the outputs)
+    if ((early_c && !kCan) || (a_parent && !kCanA)) return hipErrorInvalidValue;
     // (called while a graph is captured, once per graph)
     if (shm > 65536 && hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
