@@ -180,7 +180,10 @@ def test_batched_degenerate_and_errors(mh, ctx):
     assert mh.mh_matmul_modp_batched(ctx, d, -1, p, T, 2, 0) == mh.MH_E_INVALID
 
 
-def test_batched_subtract(mh, ctx):
+@pytest.mark.parametrize("apar", ["0", "1"])
+def test_batched_subtract(mh, ctx, monkeypatch, apar):
+    # (the A-parent form negates B's per-product panels, as the other form)
+    monkeypatch.setenv("MH_BATCH_APARENT", apar)
     p, T, N = 65521, 64, 1024
     g = np.random.default_rng(4242)
     A, B = parent_host(951, p, N), parent_host(952, p, N)

@@ -138,11 +138,12 @@ def test_queue_regrowth_after_capture(mh):
         mh.mh_ctx_destroy(ctx)
 
 
-def test_back_to_back_batches_alternating_shapes_and_moduli(mh):
-    """Batches whose kernel configuration (small or large mean output area)
-    and limb count (p = 65521 or 2^31 - 1) alternate from call to call, issued
-    without a host synchronisation in between; one synchronisation at the
-    end, then every C parent against the oracle."""
+def test_back_to_back_batches_alternating_shapes_and_moduli(mh, monkeypatch):
+    """Batches whose kernel configuration (small or large mean output area),
+    limb count (p = 65521 or 2^31 - 1) and, at two limbs, GEMM form (A from
+    per-product panels or from the parent's: MH_BATCH_APARENT) alternate
+    from call to call, issued without a host synchronisation in between; one
+    synchronisation at the end, then every C parent against the oracle."""
     torch = torch_cuda()
     N, T = 2048, 64
     P16, P31 = 65521, 2**31 - 1
@@ -162,6 +163,7 @@ def test_back_to_back_batches_alternating_shapes_and_moduli(mh):
             for p, Cs, Ds in ((P16, C16, D16), (P31, C31, D31)):
                 # mean output area below 512^2 (64 x 64 blocks), then above it
                 for smax, count in ((120, 12), (1400, 3)):
+                    monkeypatch.setenv("MH_BATCH_APARENT", str(rep % 2))
                     calls = _draw(g, count, N, 2, smax, [[], []])
                     say("alternating: rep", rep, "p", p, "smax", smax)
                     mh.check(mh.mh_matmul_modp_batched(
