@@ -103,13 +103,57 @@ def test_batched_early_c_forms(mh, ctx, monkeypatch, apar, p, T):
                           rb=int(g.integers(0, NB - k + 1)), cb=int(g.integers(0, NB - n + 1))))
     # A blocks at the parent's corners (first row and column, last row and
     # column) with C offsets whose row phase exceeds A's first row
+    # (the last two also end on C's last row, the last one on its last column)
     for i, (ra, ca, m, k) in enumerate([(0, 0, 70, 90), (NA - 45, NA - 77, 45, 77),
                                         (3, NA - 200, 90, 200), (NA - 90, 1, 90, 31)]):
         n = 50 + 20 * i
-        calls.append(dict(ci=2, rc=930 + i % 2, cc=400 + 150 * i, m=m, k=k, n=n, ra=ra, ca=ca,
+        rc = 930 + i % 2 if i < 2 else NC - m
+        cc = 400 + 150 * i if i < 3 else NC - n
+        calls.append(dict(ci=2, rc=rc, cc=cc, m=m, k=k, n=n, ra=ra, ca=ca,
                           rb=int(g.integers(0, NB - k + 1)), cb=int(g.integers(0, NB - n + 1))))
     say("batched early C", p, T, len(calls))
     run_batch(mh, ctx, calls, A, B, Cs, Ad, Bd, Cds, NA, NB, NC, p, T, 2)
+
+
+def test_batched_a_parent_two_parents(mh, ctx, monkeypatch):
+    """The A-parent form with two A parents of different sizes in one batch
+    (each packed once, each product reading its own parent's panel)."""
+    monkeypatch.setenv("MH_BATCH_APARENT", "1")
+    monkeypatch.setenv("MH_LIMB_CFG", "11")  # (small products would get configuration 6)
+    p, T = 65521, 64
+    NA1, NA2, NB, NC = 1024, 512, 1024, 1024
+    A1, A2 = parent_host(971, p, NA1), parent_host(972, p, NA2)
+    B = parent_host(973, p, NB)
+    Cs = [parent_host(974 + i, p, NC) for i in range(2)]
+    A1d, A2d = to_mh(mh, ctx, device_of(A1), NA1, T), to_mh(mh, ctx, device_of(A2), NA2, T)
+    Bd = to_mh(mh, ctx, device_of(B), NB, T)
+    Cds = [to_mh(mh, ctx, device_of(C), NC, T) for C in Cs]
+    g = np.random.default_rng(970)
+    calls, descs = [], []
+    for i in range(16):  # a 4 x 4 grid of disjoint output cells in each C parent
+        ci, cell = i % 2, i // 2
+        two = i % 3 == 0
+        NA = NA2 if two else NA1
+        m, k, n = int(g.integers(20, 250)), int(g.integers(20, 400)), int(g.integers(20, 250))
+        c = dict(ci=ci, rc=(cell % 4) * 256 + int(g.integers(0, 256 - m + 1)),
+                 cc=(cell // 4) * 256 + int(g.integers(0, 256 - n + 1)), m=m, k=k, n=n,
+                 ra=int(g.integers(0, NA - m + 1)), ca=int(g.integers(0, NA - k + 1)),
+                 rb=int(g.integers(0, NB - k + 1)), cb=int(g.integers(0, NB - n + 1)), two=two)
+        calls.append(c)
+        descs.append(dict(C=Cds[ci].data_ptr(), A=(A2d if two else A1d).data_ptr(),
+                          B=Bd.data_ptr(), NC=NC, NA=NA, NB=NB, rc=c["rc"], cc=c["cc"],
+                          ra=c["ra"], ca=c["ca"], rb=c["rb"], cb=c["cb"], m=m, k=k, n=n))
+    say("batched a-parent, two parents")
+    mh.check(mh.mh_matmul_modp_batched(ctx, mh.make_descs(descs), len(descs), p, T,
+                                       mh.MH_MODE_LIMB_I8, stream_handle()), "batched")
+    s, _, _, forms = mh.mh_ctx_last_batch_config(ctx)
+    assert forms & mh.MH_BATCH_FORM_A_PARENT
+    for c in calls:
+        Cs[c["ci"]] = expected_view(Cs[c["ci"]], A2 if c["two"] else A1, B, p, c["rc"], c["cc"],
+                                    c["ra"], c["ca"], c["rb"], c["cb"], c["m"], c["k"], c["n"])
+    for ci, Cd in enumerate(Cds):
+        assert np.array_equal(host_of(to_cart(mh, ctx, Cd, NC, T)), Cs[ci]), ci
+    assert mh.mh_ctx_last_device_error(ctx) == 0
 
 
 def test_batched_graph_replay_new_queue(mh, ctx):
