@@ -295,6 +295,17 @@ mh_status launch_batch(mh_ctx *ctx, const std::vector<Plan> &plans0, int cfg, in
             apar_of[q] = idx;
         }
         a_parent = a_parent && want != 0 && (want == 1 || words >= pwords);
+        // within the context's workspace limit: the parents' panels and the
+        // products' B panels (whose depth grows by at most one k-block)
+        if (a_parent && ctx->ws_limit) {
+            size_t need = 0;
+            for (const AParent &ap : apars)
+                need += align256(size_t(ap.nslab + kAParentGuard) * size_t(ap.nkbp) * size_t(L) *
+                                 1024);
+            for (const Plan &pl : plans0)
+                need += align256(size_t(pl.pcol) * size_t(pl.kpad + 64) * size_t(L));
+            if (need + 256 > ctx->ws_limit) a_parent = false;
+        }
     }
     // The early-C epilogue addresses C rows at any phase, so the row shift
     // need not align the output blocks with C's tile rows: none (fewer

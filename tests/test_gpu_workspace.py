@@ -156,3 +156,42 @@ def test_products_on_two_streams_share_workspace(mh):
         assert mh.mh_ctx_last_device_error(ctx) == 0
     finally:
         mh.mh_ctx_destroy(ctx)
+
+
+def test_a_parent_form_respects_workspace_limit(mh, monkeypatch):
+    """A batch that would take the A-parent form (forced with
+    MH_BATCH_APARENT=1) under a workspace limit smaller than the A parent's
+    panel (2048^2 words, two limbs: 8 MiB) runs with per-product A panels
+    instead: results exact, the workspace within the limit."""
+    monkeypatch.setenv("MH_BATCH_APARENT", "1")
+    monkeypatch.setenv("MH_LIMB_CFG", "11")
+    p, T, N = 65521, 64, 2048
+    A, B = parent_host(7301, p, N), parent_host(7302, p, N)
+    C = parent_host(7303, p, N)
+    ctx = mh.mh_ctx_create(0)
+    try:
+        mh.check(mh.mh_ctx_set_workspace_limit(ctx, 6 * MiB))
+        Ad, Bd, Cd = (to_mh(mh, ctx, device_of(X), N, T) for X in (A, B, C))
+        g = np.random.default_rng(7300)
+        calls = []
+        for i in range(8):  # disjoint cells of a 4 x 2 grid
+            m, k, n = int(g.integers(100, 400)), int(g.integers(100, 600)), int(g.integers(100, 400))
+            calls.append(dict(rc=(i % 4) * 500, cc=(i // 4) * 1000, m=m, k=k, n=n,
+                              ra=int(g.integers(0, N - m + 1)), ca=int(g.integers(0, N - k + 1)),
+                              rb=int(g.integers(0, N - k + 1)), cb=int(g.integers(0, N - n + 1))))
+        descs = mh.make_descs([dict(C=Cd.data_ptr(), A=Ad.data_ptr(), B=Bd.data_ptr(), NC=N,
+                                    NA=N, NB=N, **c) for c in calls])
+        say("a-parent under ws limit")
+        mh.check(mh.mh_matmul_modp_batched(ctx, descs, len(calls), p, T, mh.MH_MODE_LIMB_I8,
+                                           stream_handle()))
+        s, _, _, forms = mh.mh_ctx_last_batch_config(ctx)
+        assert not forms & mh.MH_BATCH_FORM_A_PARENT
+        for c in calls:
+            oracle.matmul_modp_view(C, A, B, p, c["rc"], c["cc"], c["ra"], c["ca"], c["rb"],
+                                    c["cb"], c["m"], c["k"], c["n"])
+        assert np.array_equal(host_of(to_cart(mh, ctx, Cd, N, T)), C)
+        s, limit, held = mh.mh_ctx_workspace_info(ctx)
+        assert held <= limit
+        assert mh.mh_ctx_last_device_error(ctx) == 0
+    finally:
+        mh.mh_ctx_destroy(ctx)
